@@ -1,0 +1,243 @@
+/*
+ * ttv.h -- C ABI of the MI355X (gfx950) sparse tensor-times-vector library.
+ *
+ * The operation is the mode-k product of a sparse d-way tensor with vectors
+ * (Harding & Dunlavy, "Improving Runtime Performance of Tensor Computations
+ * using Rust From Python", Sec. 3.3, Eq. 3):
+ *
+ *   (A x_k x)(i_1..i_{k-1}, i_{k+1}..i_d) = sum over i_k of a(i_1..i_d) x(i_k)
+ *
+ * A sparse tensor is stored in coordinate (COO) form: an nnz x d index array
+ * `subs`, an nnz-long value array `vals` and the dimensions `shape` (Sec. 2.1
+ * and Sec. 3.3).  The sparse result is returned as the triple the paper's
+ * pyttb procedure returns (newsubs, newvals, newshape): the distinct
+ * remaining-mode index tuples, sorted lexicographically with the first
+ * remaining mode most significant, each with the sum of its products.
+ * Multiplying by vectors in n_v modes leaves an order d - n_v tensor
+ * (Sec. 3.3); with n_v = d - 1 the result is a dense vector.
+ *
+ * Conventions for every entry point
+ *   - Indices and modes are 0-based.  Duplicate coordinates are allowed and
+ *     summed.  Exact-zero sums are kept (coordinates depend on subs only).
+ *   - "device" pointers are HIP device memory (or host memory the device can
+ *     read); "host" pointers are ordinary host memory read during the call.
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     on a call; each call takes a caller-provided workspace whose size the
+ *     matching *_workspace query returns.  Workspace contents need no
+ *     initialisation and are clobbered by the call.
+ *   - Calls are asynchronous on `stream` (0 = the null stream): arguments are
+ *     validated synchronously and a negative status is returned before
+ *     anything is enqueued.  Device-side failures are reported by
+ *     ttv_check_device_error after the work has run.
+ *   - Results are deterministic: the same inputs give bitwise-identical
+ *     outputs on every run (no floating-point atomics anywhere).
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef TTV_H
+#define TTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* ttv_stream_t; /* a hipStream_t */
+
+#define TTV_MAX_ORDER 8
+
+/* Index and value element types. */
+enum { TTV_I32 = 0, TTV_I64 = 1 };
+enum { TTV_F32 = 0, TTV_F64 = 1 };
+
+/* Status codes (0 = success, negative = error). */
+enum {
+  TTV_OK = 0,
+  TTV_E_NULL = -1,      /* a required pointer is null */
+  TTV_E_ORDER = -2,     /* d < 2 or d > TTV_MAX_ORDER */
+  TTV_E_MODE = -3,      /* mode / kept mode out of range, or repeated */
+  TTV_E_SHAPE = -4,     /* a dimension < 1, or a vector length != its dimension */
+  TTV_E_DTYPE = -5,     /* unknown index/value type, or mixed types in a batch */
+  TTV_E_KEYBITS = -6,   /* the remaining-mode indices need more than 64 key bits */
+  TTV_E_WORKSPACE = -7, /* workspace null or smaller than the query says */
+  TTV_E_INDEX = -8,     /* (device) an index was out of range (TTV_VALIDATE) */
+  TTV_E_HIP = -9,       /* a HIP runtime call failed: see ttv_last_hip_error */
+  TTV_E_SIZE = -10,     /* nnz or a dimension exceeds what this build supports */
+  TTV_E_DEVICE = -11,   /* (device) an internal bounded wait gave up */
+  TTV_E_ARG = -12       /* any other invalid argument */
+};
+
+/* Flags. */
+#define TTV_VALIDATE 0x1 /* check every index on the device (async, see ttv_check_device_error) */
+#define TTV_OUT_F64 0x2  /* FP32 inputs: write FP64 result values instead of FP32 */
+
+/*
+ * A COO sparse tensor (Sec. 3.3).  `subs` element (e, j) -- the mode-j index
+ * of nonzero e -- is read at subs[e*stride_e + j*stride_j], so row-major
+ * (stride_e = order, stride_j = 1) and column-major / structure-of-arrays
+ * (stride_e = 1, stride_j = nnz) layouts both work (the paper notes the
+ * row- vs column-major difference between its two implementations).
+ *
+ * value_dtype selects the arithmetic:
+ *   TTV_F64: FP64 vals and vectors; each product is rounded once and the
+ *            sums are FP64.  Results are FP64.
+ *   TTV_F32: FP32 vals and vectors; every product is kept exactly as an FP32
+ *            pair (TwoProduct via fmaf) and the sums are compensated FP32
+ *            (Dot2: TwoSum plus an FP32 error accumulator); partial sums of
+ *            one output that are combined across blocks are combined in
+ *            FP64.  Results are FP32 (FP64 with TTV_OUT_F64).
+ */
+typedef struct {
+  int32_t order;        /* d, 2..TTV_MAX_ORDER */
+  int32_t index_dtype;  /* TTV_I32 or TTV_I64 */
+  int32_t value_dtype;  /* TTV_F32 or TTV_F64 */
+  int32_t reserved;     /* set to 0 */
+  int64_t nnz;          /* >= 0 */
+  int64_t shape[TTV_MAX_ORDER]; /* host values, shape[j] >= 1 for j < order */
+  const void* subs;     /* device */
+  int64_t stride_e;     /* in elements */
+  int64_t stride_j;     /* in elements */
+  const void* vals;     /* device, nnz contiguous values */
+} ttv_coo_desc;
+
+/* Key layout and pass plan of a product (host only; for tests and logging). */
+typedef struct {
+  int32_t order, nrem, key_bits, levels;
+  int32_t rem_modes[TTV_MAX_ORDER]; /* remaining modes, ascending */
+  int32_t bits[TTV_MAX_ORDER];      /* key bits of each remaining mode */
+  int32_t shift[TTV_MAX_ORDER];     /* bit position of each remaining mode */
+  int32_t digit1_bits;              /* bits of the first bucket level */
+  int32_t reserved;
+  int64_t workspace_bytes;
+} ttv_plan_info;
+
+/* Human-readable text of a status code (static storage). */
+const char* ttv_strerror(int status);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int ttv_version(void);
+
+/* hipError_t of the most recent failing HIP call on this thread (0 if none). */
+int ttv_last_hip_error(void);
+
+/*
+ * Host-only planning of the product that contracts the modes in `modes`
+ * (ncon entries, distinct): which modes remain, how their indices pack into
+ * a sort key (first remaining mode most significant, so numeric key order is
+ * lexicographic order -- the `unique` step of Sec. 3.3), how many bucket
+ * levels the key needs, and the workspace size.  Touches no device.
+ */
+int ttv_plan_query(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes,
+                   int32_t flags, ttv_plan_info* out);
+
+/* ------------------------------------------------------------------------
+ * Sparse TTV in one mode (Eq. 3).
+ *   v        device, v_len = shape[mode] values of X's value type
+ *   out_subs device, capacity nnz x (d-1) indices of X's index type; row r
+ *            holds the remaining-mode indices of output r in ascending mode
+ *            order (row-major)
+ *   out_vals device, capacity nnz values (FP64 for TTV_F64; FP32 for TTV_F32
+ *            unless TTV_OUT_F64, then FP64)
+ *   out_nnz  device int64 scalar: the number of output rows (<= nnz)
+ *   newshape is shape without `mode` (computed by the caller).
+ * ---------------------------------------------------------------------- */
+int ttv_coo_workspace(const ttv_coo_desc* X, int32_t mode, int32_t flags, size_t* bytes);
+int ttv_coo(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len,
+            void* out_subs, void* out_vals, int64_t* out_nnz,
+            void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Sparse TTV with vectors in several modes (n_v = ncon vectors, Sec. 3.3):
+ * the result is sparse of order d - ncon (1 <= ncon <= d - 1).
+ *   modes  host, ncon distinct contracted modes
+ *   vecs   host array of ncon device pointers, vecs[i] has shape[modes[i]]
+ * Output as for ttv_coo with d - ncon index columns.
+ * ---------------------------------------------------------------------- */
+int ttv_coo_multi_workspace(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes,
+                            int32_t flags, size_t* bytes);
+int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes,
+                  const void* const* vecs, const int64_t* vec_lens,
+                  void* out_subs, void* out_vals, int64_t* out_nnz,
+                  void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * All-but-one product (n_v = d - 1, Sec. 3.3): a dense vector
+ *   y[i] = sum over nonzeros e with subs(e, keep) = i of
+ *          vals[e] * prod_{j != keep} vecs[j][subs(e, j)]
+ * (factors multiplied in ascending mode order).  Entries no nonzero reaches
+ * are 0.  Accumulation is atomics-free: every block reduces its tiles into a
+ * private dense partial, and the partials are summed in a fixed order.
+ *   vecs     host array of d device pointers (vecs[keep] is ignored)
+ *   vec_lens host array of d lengths (vec_lens[keep] is ignored)
+ *   y        device, shape[keep] values (FP64, or FP32 unless TTV_OUT_F64)
+ * ---------------------------------------------------------------------- */
+int ttv_coo_allbut_workspace(const ttv_coo_desc* X, int32_t keep, int32_t flags, size_t* bytes);
+int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
+                   const int64_t* vec_lens, void* y,
+                   void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoints (reverse mode).  Eq. 3 is linear in the vector and in vals, so
+ *   TTV_BWD_SPARSE  (the product of ttv_coo in mode `mode_or_keep`):
+ *     grad_out  device, one value per output row of ttv_coo, in its order
+ *     grad_vecs[mode][j] = sum over e with subs(e, mode) = j of vals[e] * g[row(e)]
+ *     grad_vals[e]       = v[subs(e, mode)] * g[row(e)]
+ *   TTV_BWD_ALLBUT  (the product of ttv_coo_allbut keeping `mode_or_keep`):
+ *     grad_out  device, shape[keep] values
+ *     grad_vals[e]    = g[subs(e, keep)] * prod_{j != keep} vecs[j][subs(e, j)]
+ *     grad_vecs[m][i] = sum over e with subs(e, m) = i of
+ *                       vals[e] * g[subs(e, keep)] * prod_{j != keep, m} vecs[j][subs(e, j)]
+ *   vecs, vec_lens  as for the forward (host arrays of d entries)
+ *   grad_vecs       host array of d device pointers; null entries are skipped
+ *   grad_vals       device, nnz values, or null to skip
+ * grad_out and every gradient have X's value type (FP32 gradients of the
+ * FP32 form are rounded once from compensated / FP64-combined values).
+ * ---------------------------------------------------------------------- */
+enum { TTV_BWD_SPARSE = 0, TTV_BWD_ALLBUT = 1 };
+int ttv_coo_backward_workspace(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep,
+                               int32_t flags, size_t* bytes);
+int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep,
+                     const void* const* vecs, const int64_t* vec_lens,
+                     const void* grad_out, void* const* grad_vecs, void* grad_vals,
+                     void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched sparse TTV: `count` independent tensors, each with its own mode
+ * and vector, all run by one fixed sequence of persistent kernels.  A plan
+ * binds the tensors, vectors and outputs (all device pointers stay fixed) so
+ * that ttv_coo_batched does no host synchronisation, no allocation and no
+ * host read of device results: it may be captured into a hipGraph and
+ * replayed.  All tensors must share index and value types.
+ *   Xs        host array of count descriptors
+ *   modes     host array of count modes
+ *   vs        host array of count device vectors
+ *   out_subs, out_vals  host arrays of count device outputs (as ttv_coo)
+ *   out_nnz   device array of count int64 results
+ *   tune_cache  path of the autotuner's JSON cache, or null
+ * ttv_batch_autotune times candidate tile sizes and digit widths on the
+ * bound batch (running it several times on `stream` and synchronising),
+ * keeps the fastest in the plan and records it in the cache file.
+ * ---------------------------------------------------------------------- */
+typedef struct ttv_batch_plan ttv_batch_plan;
+int ttv_batch_plan_create(int32_t count, const ttv_coo_desc* Xs, const int32_t* modes,
+                          const void* const* vs, void* const* out_subs,
+                          void* const* out_vals, int64_t* out_nnz, int32_t flags,
+                          const char* tune_cache, ttv_batch_plan** plan);
+int ttv_batch_workspace(const ttv_batch_plan* plan, size_t* bytes);
+int ttv_batch_autotune(ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_stream_t stream);
+int ttv_coo_batched(const ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_stream_t stream);
+void ttv_batch_plan_destroy(ttv_batch_plan* plan);
+
+/*
+ * Synchronises `stream` and returns the first device-side error recorded in
+ * workspace `ws` by the last call that used it (TTV_OK if none), e.g.
+ * TTV_E_INDEX for an out-of-range index under TTV_VALIDATE.
+ */
+int ttv_check_device_error(const void* ws, ttv_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTV_H */

@@ -1,0 +1,12 @@
+"""Sparse tensor-times-vector on AMD MI355X (gfx950).
+
+The product of Eq. 3 in Harding & Dunlavy (Sec. 3.3) on COO sparse tensors,
+computed by hand-written HIP kernels behind a C ABI (``include/ttv.h``).
+This package holds the ctypes binding and a thin PyTorch-facing API; PyTorch
+only supplies device memory and streams.
+"""
+
+from . import _lib  # noqa: F401
+from .api import TTVOp, coo_desc, plan_query, ttv, ttv_multi  # noqa: F401
+
+__all__ = ["TTVOp", "coo_desc", "plan_query", "ttv", "ttv_multi"]

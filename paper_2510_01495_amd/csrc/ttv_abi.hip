@@ -1,0 +1,288 @@
+// C ABI: argument validation, key-layout planning, workspace layout and
+// dispatch of the sparse TTV pipeline (Eq. 3, Sec. 3.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "ttv.h"
+#include "ttv_host.h"
+
+namespace ttv {
+
+static thread_local int g_last_hip_error = 0;
+void set_last_hip_error(int e) { g_last_hip_error = e; }
+
+int device_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> g(mu);
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
+static int bitlen(unsigned long long x) {
+  int b = 0;
+  while (x) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Validates a descriptor and fills the tensor part of a TDesc: remaining
+// modes (all modes minus the contracted ones, ascending -- the set
+// difference of Sec. 3.3), their key fields (first remaining mode most
+// significant, so numeric key order is lexicographic tuple order) and the
+// first-level digit.
+int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, TDesc& D, int& form,
+                int& idx64) {
+  if (!X || !modes) return TTV_E_NULL;
+  const int d = X->order;
+  if (d < 2 || d > TTV_MAX_ORDER) return TTV_E_ORDER;
+  if (X->index_dtype != TTV_I32 && X->index_dtype != TTV_I64) return TTV_E_DTYPE;
+  if (X->value_dtype != TTV_F32 && X->value_dtype != TTV_F64) return TTV_E_DTYPE;
+  if (X->nnz < 0) return TTV_E_ARG;
+  if (X->nnz > 0x7fffffffLL) return TTV_E_SIZE;
+  for (int j = 0; j < d; ++j)
+    if (X->shape[j] < 1) return TTV_E_SHAPE;
+  if (X->index_dtype == TTV_I32)
+    for (int j = 0; j < d; ++j)
+      if (X->shape[j] > 0x7fffffffLL) return TTV_E_SIZE;
+  if (X->nnz > 0 && (!X->subs || !X->vals)) return TTV_E_NULL;
+  if (ncon < 1 || ncon > d - 1) return TTV_E_MODE;
+  bool con[TTV_MAX_ORDER] = {false};
+  for (int c = 0; c < ncon; ++c) {
+    if (modes[c] < 0 || modes[c] >= d || con[modes[c]]) return TTV_E_MODE;
+    con[modes[c]] = true;
+  }
+  std::memset(&D, 0, sizeof(D));
+  D.subs = X->subs;
+  D.vals = X->vals;
+  D.nnz = X->nnz;
+  D.stride_e = X->stride_e;
+  D.stride_j = X->stride_j;
+  D.order = d;
+  for (int j = 0; j < d; ++j) D.dims[j] = X->shape[j];
+  int nr = 0, nc = 0;
+  for (int j = 0; j < d; ++j) {
+    if (con[j])
+      D.con[nc++] = j;
+    else
+      D.rem[nr++] = j;
+  }
+  D.nrem = nr;
+  D.ncon = nc;
+  int bits = 0;
+  for (int i = 0; i < nr; ++i) {
+    D.width[i] = bitlen((unsigned long long)(X->shape[D.rem[i]] - 1));
+    bits += D.width[i];
+  }
+  if (bits > 64) return TTV_E_KEYBITS;
+  D.keybits = bits;
+  int sh = 0;
+  for (int i = nr - 1; i >= 0; --i) {
+    D.shift[i] = sh;
+    sh += D.width[i];
+  }
+  // first digit: expected bucket about 0.6 * kSmall records
+  int r1 = 0;
+  const double target = 0.6 * kSmall;
+  while (r1 < kRMax && r1 < bits && (double)X->nnz / (double)(1LL << r1) > target) ++r1;
+  D.r1 = r1;
+  int nd = 0;
+  for (int i = 0; i < nr; ++i)
+    if (D.shift[i] + D.width[i] > bits - r1 && D.width[i] > 0) nd = i + 1;
+  D.ndig_modes = r1 > 0 ? nd : 0;
+  D.validate = (flags & TTV_VALIDATE) ? 1 : 0;
+  D.out_f64 = (flags & TTV_OUT_F64) ? 1 : 0;
+  form = X->value_dtype == TTV_F64 ? kF64 : kC32;
+  idx64 = X->index_dtype == TTV_I64 ? 1 : 0;
+  return TTV_OK;
+}
+
+static int levels_of(const TDesc& D) {
+  const int rest = std::max(0, D.keybits - D.r1);
+  return std::min(kMaxLevels, 1 + (rest + kRMax - 1) / kRMax);
+}
+
+Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1) {
+  Layout L{};
+  L.count = count;
+  L.levels = levels;
+  L.jcap = std::max<long long>(count, total / kCap + 2);
+  L.tcap = std::max<long long>(tiles1, total / T2 + L.jcap + 1);
+  L.lcap = (long long)levels * (3 * ((total + kSmall - 1) / kSmall) + L.jcap) + count + 64;
+  L.pcap = total / kPureTile + total / kCap + count + 2;
+  L.words = (total + 31) / 32 + 1;
+  L.wblocks = (L.words + 8191) / 8192;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.ctrl = take(sizeof(Ctrl));
+  L.desc = take((size_t)std::max(count, 1) * sizeof(TDesc));
+  L.jobs = take((size_t)levels * L.jcap * sizeof(Job));
+  L.tiles = take((size_t)levels * L.tcap * sizeof(int));
+  L.table = take((size_t)L.tcap * kNDig * sizeof(unsigned));
+  L.starts = take((size_t)L.jcap * kNDig * sizeof(unsigned));
+  L.leaves = take((size_t)L.lcap * sizeof(Leaf));
+  L.ordered = take((size_t)L.lcap * sizeof(Leaf));
+  L.status = take((size_t)L.lcap * sizeof(unsigned long long));
+  L.bitmap = take((size_t)L.words * sizeof(unsigned));
+  L.wordpre = take((size_t)L.words * sizeof(unsigned));
+  L.blockpre = take((size_t)L.wblocks * sizeof(unsigned));
+  L.partials = take((size_t)L.pcap * sizeof(double));
+  L.ptile_leaf = take((size_t)L.pcap * sizeof(int));
+  L.recA = take((size_t)total * sizeof(Rec));
+  L.recB = take(levels > 1 ? (size_t)total * sizeof(Rec) : 0);
+  L.end = o;
+  return L;
+}
+
+static int choose_T1(long long total) {
+  long long t = (total + 2 * 256 - 1) / (2 * 256);
+  t = (t + 1023) / 1024 * 1024;
+  return (int)std::min<long long>(65536, std::max<long long>(4096, t));
+}
+
+// Plans a single-tensor pipeline run (ncon contracted modes).
+int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, int pipe_mode,
+                PipePlan& P) {
+  int rc = plan_tensor(X, ncon, modes, flags, P.d0, P.form, P.idx64);
+  if (rc) return rc;
+  P.count = 1;
+  P.pipe_mode = pipe_mode;
+  P.total = X->nnz;
+  P.d0.base = 0;
+  P.levels = levels_of(P.d0);
+  P.T1 = choose_T1(P.total);
+  P.T2 = 16384;
+  P.tiles1 = (P.total + P.T1 - 1) / P.T1;
+  P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1);
+  return TTV_OK;
+}
+
+}  // namespace ttv
+
+using namespace ttv;
+
+extern "C" {
+
+const char* ttv_strerror(int s) {
+  switch (s) {
+    case TTV_OK: return "success";
+    case TTV_E_NULL: return "a required pointer is null";
+    case TTV_E_ORDER: return "tensor order must be in [2, TTV_MAX_ORDER]";
+    case TTV_E_MODE: return "mode out of range or repeated";
+    case TTV_E_SHAPE: return "invalid dimension or vector length";
+    case TTV_E_DTYPE: return "unsupported or mixed index/value type";
+    case TTV_E_KEYBITS: return "remaining-mode indices need more than 64 key bits";
+    case TTV_E_WORKSPACE: return "workspace missing or too small";
+    case TTV_E_INDEX: return "an index is out of range";
+    case TTV_E_HIP: return "a HIP runtime call failed";
+    case TTV_E_SIZE: return "size beyond what this build supports";
+    case TTV_E_DEVICE: return "a device-side bounded wait or capacity check failed";
+    case TTV_E_ARG: return "invalid argument";
+    default: return "unknown status";
+  }
+}
+
+int ttv_version(void) { return 100; }
+
+int ttv_last_hip_error(void) { return g_last_hip_error; }
+
+int ttv_plan_query(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, int32_t flags,
+                   ttv_plan_info* out) {
+  if (!out) return TTV_E_NULL;
+  PipePlan P;
+  const int rc = plan_single(X, ncon, modes, flags, kPipeTTV, P);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->order = P.d0.order;
+  out->nrem = P.d0.nrem;
+  out->key_bits = P.d0.keybits;
+  out->levels = P.levels;
+  for (int i = 0; i < P.d0.nrem; ++i) {
+    out->rem_modes[i] = P.d0.rem[i];
+    out->bits[i] = P.d0.width[i];
+    out->shift[i] = P.d0.shift[i];
+  }
+  out->digit1_bits = P.d0.r1;
+  out->workspace_bytes = (int64_t)P.L.end;
+  return TTV_OK;
+}
+
+int ttv_coo_multi_workspace(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, int32_t flags,
+                            size_t* bytes) {
+  if (!bytes) return TTV_E_NULL;
+  PipePlan P;
+  const int rc = plan_single(X, ncon, modes, flags, kPipeTTV, P);
+  if (rc) return rc;
+  *bytes = P.L.end;
+  return TTV_OK;
+}
+
+int ttv_coo_workspace(const ttv_coo_desc* X, int32_t mode, int32_t flags, size_t* bytes) {
+  return ttv_coo_multi_workspace(X, 1, &mode, flags, bytes);
+}
+
+int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, const void* const* vecs,
+                  const int64_t* vec_lens, void* out_subs, void* out_vals, int64_t* out_nnz, void* ws,
+                  size_t ws_bytes, int32_t flags, ttv_stream_t stream) {
+  PipePlan P;
+  int rc = plan_single(X, ncon, modes, flags, kPipeTTV, P);
+  if (rc) return rc;
+  if (!vecs || !vec_lens || !out_nnz) return TTV_E_NULL;
+  for (int c = 0; c < ncon; ++c) {
+    if (vec_lens[c] != X->shape[modes[c]]) return TTV_E_SHAPE;
+    if (!vecs[c] && X->nnz > 0) return TTV_E_NULL;
+    P.d0.vec[modes[c]] = vecs[c];
+  }
+  if (X->nnz > 0 && (!out_subs || !out_vals)) return TTV_E_NULL;
+  if (!ws || ws_bytes < P.L.end) return TTV_E_WORKSPACE;
+  P.d0.out_subs = out_subs;
+  P.d0.out_vals = out_vals;
+  P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
+  P.cus = device_cus();
+  return launch_pipeline(P, ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+int ttv_coo(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len, void* out_subs,
+            void* out_vals, int64_t* out_nnz, void* ws, size_t ws_bytes, int32_t flags,
+            ttv_stream_t stream) {
+  const void* vecs[1] = {v};
+  const int64_t lens[1] = {v_len};
+  return ttv_coo_multi(X, 1, &mode, vecs, lens, out_subs, out_vals, out_nnz, ws, ws_bytes, flags, stream);
+}
+
+int ttv_check_device_error(const void* ws, ttv_stream_t stream) {
+  if (!ws) return TTV_E_NULL;
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  int32_t err = 0;
+  e = hipMemcpy(&err, static_cast<const char*>(ws) + offsetof(Ctrl, error), sizeof(err), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  return err;
+}
+
+}  // extern "C"

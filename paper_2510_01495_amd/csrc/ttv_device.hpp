@@ -1,0 +1,180 @@
+// Device primitives for gfx950 (CDNA4, wave64): lane masks, ballot
+// multisplit, DPP prefix scans, error-free FP32 transforms and the two
+// value forms (FP64, compensated FP32).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ttv_internal.h"
+
+namespace ttv {
+
+// ---------------------------------------------------------------------------
+// Lanes and masks
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// Number of set bits of m in the lanes below this one.
+__device__ __forceinline__ unsigned count_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Lanes of `valid` whose r-bit digit equals this lane's (ballot multisplit:
+// one ballot per digit bit, keep the lanes that agree on every bit).
+__device__ __forceinline__ uint64_t match_digit(unsigned d, int r, uint64_t valid) {
+  uint64_t m = valid;
+  for (int b = 0; b < r; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// DPP wave prefix sums (u32).  Rows of 16 lanes scan with row_shr 1/2/4/8,
+// then row_bcast:15 and row_bcast:31 carry the row totals across rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+__device__ __forceinline__ unsigned wave_total(unsigned incl) {
+  return (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+}
+
+// Block-wide exclusive scan of one u32 per thread.  `wsum` holds NT/64
+// entries of LDS.  Returns the exclusive prefix; `total` gets the block sum.
+template <int NT>
+__device__ __forceinline__ unsigned block_excl_scan(unsigned v, unsigned* wsum, unsigned& total) {
+  const unsigned inc = wave_incl_scan(v);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) wsum[w] = inc;
+  __syncthreads();
+  unsigned off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const unsigned s = wsum[i];
+    off += (i < w) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return off + inc - v;
+}
+
+template <int NT>
+__device__ __forceinline__ unsigned block_sum(unsigned v, unsigned* wsum) {
+  unsigned t;
+  block_excl_scan<NT>(v, wsum, t);
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Error-free transformations (Knuth's TwoSum; TwoProduct through fmaf) and
+// the Dot2 accumulator of Ogita, Rump and Oishi ("Accurate Sum and Dot
+// Product", SISC 2005): the running sum s plus an FP32 accumulator c of the
+// exact rounding errors.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+struct C2 {
+  float s, c;
+};
+
+// ---------------------------------------------------------------------------
+// Value forms.  A record payload is 64 bits: an FP64 product, or the FP32
+// pair (hi, lo) with hi + lo the exact product of FP32 inputs.
+// ---------------------------------------------------------------------------
+template <int F>
+struct FormOps;
+
+template <>
+struct FormOps<kF64> {
+  using In = double;
+  using Acc = double;
+  static __device__ __forceinline__ Acc zero() { return 0.0; }
+  static __device__ __forceinline__ Acc from_pay(uint64_t p) { return __longlong_as_double((long long)p); }
+  static __device__ __forceinline__ Acc add(Acc a, Acc b) { return a + b; }
+  static __device__ __forceinline__ double to_f64(Acc a) { return a; }
+  // product of the value with the vector entries of the contracted modes
+  static __device__ __forceinline__ uint64_t start_prod(In a) { return (uint64_t)__double_as_longlong(a); }
+  static __device__ __forceinline__ uint64_t mul_prod(uint64_t p, In x) {
+    return (uint64_t)__double_as_longlong(__longlong_as_double((long long)p) * x);
+  }
+  static __device__ __forceinline__ Acc shfl_up(Acc a, int d) { return __shfl_up(a, d, 64); }
+};
+
+template <>
+struct FormOps<kC32> {
+  using In = float;
+  using Acc = C2;
+  static __device__ __forceinline__ Acc zero() { return C2{0.f, 0.f}; }
+  static __device__ __forceinline__ Acc from_pay(uint64_t p) {
+    return C2{__uint_as_float((unsigned)p), __uint_as_float((unsigned)(p >> 32))};
+  }
+  static __device__ __forceinline__ uint64_t make_pay(float hi, float lo) {
+    return (uint64_t)__float_as_uint(hi) | ((uint64_t)__float_as_uint(lo) << 32);
+  }
+  // Dot2 combination of two partial sums: TwoSum of the leading parts, the
+  // error terms added in FP32.
+  static __device__ __forceinline__ Acc add(Acc a, Acc b) {
+    float s, q;
+    two_sum(a.s, b.s, s, q);
+    return C2{s, (a.c + b.c) + q};
+  }
+  static __device__ __forceinline__ double to_f64(Acc a) { return (double)a.s + (double)a.c; }
+  // Compensated product: TwoProduct of the leading part, the error term
+  // carried and scaled by every further factor.
+  static __device__ __forceinline__ uint64_t start_prod(In a) { return make_pay(a, 0.f); }
+  static __device__ __forceinline__ uint64_t mul_prod(uint64_t p, In x) {
+    const C2 v = from_pay(p);
+    float hi, e;
+    two_prod(v.s, x, hi, e);
+    return make_pay(hi, __builtin_fmaf(v.c, x, e));
+  }
+  static __device__ __forceinline__ Acc shfl_up(Acc a, int d) {
+    return C2{__shfl_up(a.s, d, 64), __shfl_up(a.c, d, 64)};
+  }
+};
+
+// Segmented-scan element: `f` marks that a segment head lies inside.
+template <int F>
+struct Seg {
+  typename FormOps<F>::Acc v;
+  int f;
+};
+template <int F>
+__device__ __forceinline__ Seg<F> seg_combine(const Seg<F>& a, const Seg<F>& b) {
+  Seg<F> r;
+  r.f = a.f | b.f;
+  r.v = b.f ? b.v : FormOps<F>::add(a.v, b.v);
+  return r;
+}
+
+// Index loads from either index type.
+template <typename IdxT>
+__device__ __forceinline__ long long ld_idx(const TDesc& D, long long e, int j) {
+  return (long long)static_cast<const IdxT*>(D.subs)[e * D.stride_e + (long long)j * D.stride_j];
+}
+
+__device__ __forceinline__ void set_error(Ctrl* C, int code) { atomicCAS(&C->error, 0, code); }
+
+__device__ __forceinline__ int bitlen64(unsigned long long x) { return x ? 64 - __clzll((long long)x) : 0; }
+
+}  // namespace ttv

@@ -1,0 +1,127 @@
+// Internal layout shared by the host planner and the gfx950 kernels.
+//
+// The sparse TTV of Eq. 3 (Sec. 3.3) is computed as a keyed reduction: every
+// nonzero becomes a 16-byte record (key, payload) whose key packs the indices
+// of the modes that survive the product and whose payload is the product of
+// the value with the vector entries of the contracted modes.  Records are
+// bucketed by the key's most significant bits (one or more scatter levels),
+// every bucket that fits in LDS is sorted there and reduced, and the unique
+// keys are unpacked into the output coordinates in lexicographic order.
+#pragma once
+
+#include <stdint.h>
+
+#include "ttv.h"
+
+namespace ttv {
+
+constexpr int kWave = 64;
+constexpr int kMaxOrder = TTV_MAX_ORDER;
+constexpr int kRMax = 12;                // digit bits per bucket level
+constexpr int kNDig = 1 << kRMax;        // row stride of the per-tile digit tables
+constexpr int kCap = 8192;               // most records an LDS leaf holds
+constexpr int kSmall = kCap / 2;         // buckets up to this size are merged into chunks
+constexpr int kMaxLevels = 8;            // 64-bit keys with 12-bit digits need at most 6
+constexpr int kPureTile = 16384;         // records per block when reducing a single-key bucket
+constexpr int kScatterThreads = 256;     // 4 waves
+constexpr int kScatterIPT = 8;           // records per thread per round
+constexpr int kFinishThreads = 512;      // 8 waves
+constexpr int kFinishIPT = kCap / kFinishThreads;
+constexpr int kSortDigit = 8;            // LDS radix digit width
+
+// Value forms.
+enum Form : int32_t {
+  kF64 = 0,  // FP64 inputs, FP64 products and sums
+  kC32 = 1,  // FP32 inputs, exact FP32 product pairs, Dot2 compensated sums
+};
+
+// Where the records of a job or leaf live.
+enum Src : int32_t { kSrcRaw = 0, kSrcA = 1, kSrcB = 2 };
+
+// Output / operation modes of the keyed-reduction pipeline.
+enum PipeMode : int32_t {
+  kPipeTTV = 0,     // sparse output: coordinates + summed values
+  kPipeSegMap = 1,  // no values: for every input nonzero, the output row it lands in
+};
+
+struct Rec {
+  uint64_t key;
+  uint64_t pay;
+};
+
+// Per-tensor description, resident in the workspace.
+struct TDesc {
+  const void* subs;
+  const void* vals;
+  const void* vec[kMaxOrder];   // vector of every contracted mode (null elsewhere)
+  void* out_subs;               // (nnz_out, nrem) row-major, index dtype of the input
+  void* out_vals;               // nnz_out values
+  long long* out_nnz;           // device scalar
+  int32_t* seg_out;             // segment map (kPipeSegMap)
+  long long nnz;
+  long long base;               // first record of this tensor in the record buffers
+  long long stride_e, stride_j; // subs element (e, j) at subs[e*stride_e + j*stride_j]
+  long long dims[kMaxOrder];
+  int32_t order;
+  int32_t nrem;                 // remaining (kept) modes
+  int32_t ncon;                 // contracted modes
+  int32_t keybits;
+  int32_t rem[kMaxOrder];       // remaining modes, ascending; rem[0] is most significant
+  int32_t shift[kMaxOrder];     // bit position of each remaining mode's field
+  int32_t width[kMaxOrder];
+  int32_t con[kMaxOrder];       // contracted modes, ascending
+  int32_t r1;                   // digit bits of the first level
+  int32_t ndig_modes;           // leading remaining modes that overlap the first digit
+  int32_t out_f64;              // compensated form writes FP64 values
+  int32_t validate;             // check every index against dims
+};
+
+// A bucket that is split by the next digit.
+struct Job {
+  long long start;        // global record position
+  long long size;
+  unsigned long long prefix;  // key bits above this job's digit
+  long long tile0;        // first tile of this job in the level's tile list
+  int32_t ntiles;
+  int32_t tensor;
+  int32_t shift;          // lowest bit of this job's digit
+  int32_t r;              // digit bits
+  int32_t src;            // where the records are read from
+  int32_t pad;
+};
+
+// A range of records reduced by one finishing block.
+enum LeafKind : int32_t { kLeafSort = 0, kLeafPure = 1 };
+struct Leaf {
+  long long start;
+  long long size;
+  unsigned long long base;  // smallest key of the leaf: relative keys are key - base
+  long long ptile0;         // pure leaves: first partial
+  int32_t nptiles;
+  int32_t tensor;
+  int32_t kind;
+  int32_t src;
+  int32_t bits;             // bits of the relative keys
+  int32_t pad;
+};
+
+// Device-side counters, zeroed by the init kernel of every call.
+struct Ctrl {
+  int32_t njobs[kMaxLevels + 1];
+  int32_t ntiles[kMaxLevels + 1];
+  int32_t nleaves;
+  int32_t npure;
+  int32_t ticket;
+  int32_t error;          // first device-side error (TTV_E_* code), 0 if none
+  long long total;        // records over all tensors
+};
+
+// Byte offsets of every region inside the caller's workspace.
+struct Layout {
+  size_t ctrl, desc, jobs, tiles, table, starts, leaves, ordered, status;
+  size_t bitmap, wordpre, blockpre, partials, ptile_leaf, recA, recB, end;
+  long long jcap, tcap, lcap, pcap, words, wblocks;
+  int32_t count, levels;
+};
+
+}  // namespace ttv

@@ -1,0 +1,247 @@
+"""GPU parity of ttv_coo / ttv_coo_multi against the FP64 CPU oracle.
+
+Coordinates must match bit for bit; FP64 values within 1e-12 (relative to
+the sum of |products| of each output, which is the relative error for the
+all-positive workloads); compensated FP32 values within 1e-6."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import check_ttv, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+C32_TOL = 1e-6
+
+
+def _api():
+    import paper_2510_01495_amd as P
+    return P
+
+
+def _cases():
+    out = []
+    for d in (2, 3, 4, 5):
+        for seed in range(4):
+            rng = np.random.default_rng(77 * d + seed)
+            dims = [int(x) for x in rng.integers(1, 12, size=d)]
+            nnz = int(rng.integers(0, 400))
+            out.append((d, seed, dims, nnz))
+    return out
+
+
+@pytest.mark.parametrize("d,seed,dims,nnz", _cases())
+@pytest.mark.parametrize("idx", ["i64", "i32"])
+def test_tiny_all_modes_f64(d, seed, dims, nnz, idx):
+    P = _api()
+    X = synth.tiny(900 + 10 * d + seed, d, dims, nnz,
+                   index_dtype=np.int64 if idx == "i64" else np.int32)
+    subs, vals = to_gpu(X)
+    for mode in range(d):
+        v = np.random.default_rng(seed + mode).random(dims[mode])
+        say(f"tiny d={d} seed={seed} dims={dims} nnz={nnz} mode={mode} idx={idx}")
+        (gv_,) = to_gpu(X, v)[2:]
+        gs, gv, shp = P.ttv(subs, vals, X.shape, mode, gv_)
+        assert shp == tuple(s for j, s in enumerate(X.shape) if j != mode)
+        check_ttv(X, mode, v, gs, gv, F64_TOL, f"d={d} mode={mode}")
+
+
+def test_hand_example_exact():
+    P = _api()
+    X = synth.COO(np.array([[0, 0, 0], [0, 1, 0], [1, 0, 1], [1, 1, 1], [0, 0, 1]]),
+                  np.array([1.0, 2.0, 3.0, 4.0, 5.0]), (2, 2, 2))
+    v = np.array([10.0, 100.0])
+    subs, vals, gv_ = to_gpu(X, v)
+    for mode in range(3):
+        gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+        ns, nv, _ = oracle.ttv(X.subs, X.vals, X.shape, mode, v)
+        assert np.array_equal(gs.cpu().numpy(), ns) and np.array_equal(gv.cpu().numpy(), nv)
+
+
+def test_integer_values_bitwise():
+    """Small-integer data: every summation order is exact, so GPU == oracle bitwise."""
+    P = _api()
+    for seed in range(3):
+        X = synth.tiny(1200 + seed, 4, (9, 7, 11, 5), 3000, value_dist="int_f64")
+        for mode in range(4):
+            v = np.random.default_rng(seed).integers(-4, 5, X.shape[mode]).astype(np.float64)
+            subs, vals, gv_ = to_gpu(X, v)
+            gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+            ns, nv, _ = oracle.ttv(X.subs, X.vals, X.shape, mode, v)
+            assert np.array_equal(gs.cpu().numpy(), ns)
+            assert np.array_equal(gv.cpu().numpy(), nv)
+
+
+def test_small_workload_every_mode():
+    P = _api()
+    X, mode0, v0 = synth.workload_small()
+    subs, vals = to_gpu(X)
+    for mode in range(3):
+        v = v0 if mode == mode0 else np.random.default_rng(mode).random(X.shape[mode])
+        say(f"100x80x60 nnz=1e4 mode={mode}")
+        (gv_,) = to_gpu(X, v)[2:]
+        gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+        rel, _ = check_ttv(X, mode, v, gs, gv, F64_TOL, f"small mode {mode}")
+        assert rel <= F64_TOL
+
+
+def test_column_major_subs():
+    P = _api()
+    X = synth.tiny(31, 3, (40, 30, 20), 5000)
+    v = np.random.default_rng(3).random(30)
+    subs, vals, gv_ = to_gpu(X, v, soa=True)
+    assert subs.stride(0) == 1
+    gs, gv, _ = P.ttv(subs, vals, X.shape, 1, gv_)
+    check_ttv(X, 1, v, gs, gv, F64_TOL, "soa")
+
+
+def test_empty_and_size_one_modes():
+    P = _api()
+    import torch
+    X = synth.COO(np.zeros((0, 3), dtype=np.int64), np.zeros(0), (4, 5, 6))
+    subs, vals, gv_ = to_gpu(X, np.ones(5))
+    gs, gv, shp = P.ttv(subs, vals, X.shape, 1, gv_)
+    assert gs.shape == (0, 2) and gv.shape == (0,) and shp == (4, 6)
+    # size-1 remaining modes: every nonzero has the same key (one output row)
+    X = synth.tiny(5, 3, (1, 50, 1), 20000)
+    v = np.random.default_rng(0).random(50)
+    subs, vals, gv_ = to_gpu(X, v)
+    gs, gv, _ = P.ttv(subs, vals, X.shape, 1, gv_)
+    check_ttv(X, 1, v, gs, gv, F64_TOL, "single key")
+    assert torch.cuda.is_available()
+
+
+def test_multi_vector_product():
+    P = _api()
+    X = synth.tiny(44, 4, (10, 12, 9, 8), 4000)
+    rng = np.random.default_rng(9)
+    vecs = [rng.random(s) for s in X.shape]
+    subs, vals = to_gpu(X)
+    for modes in ([0, 2], [1, 3], [0, 1, 3], [3, 0]):
+        gvecs = to_gpu(X, *[vecs[m] for m in modes])[2:]
+        gs, gv, shp = P.ttv_multi(subs, vals, X.shape, modes, gvecs)
+        # oracle: repeated single-vector products, highest mode first
+        s, a, shape, left = X.subs, X.vals, list(X.shape), list(range(4))
+        for m in sorted(modes, reverse=True):
+            pos = left.index(m)
+            s, a, shape = oracle.ttv(s, a, tuple(shape), pos, vecs[m])
+            shape = list(shape)
+            left.pop(pos)
+        assert np.array_equal(gs.cpu().numpy(), s)
+        np.testing.assert_allclose(gv.cpu().numpy(), a, rtol=1e-12)
+
+
+@pytest.mark.parametrize("scale", [0.01, 0.05])
+def test_uniform_scaled(scale):
+    """10^4 cube, uniform distinct coordinates, scaled nnz: every mode."""
+    P = _api()
+    X, vecs = synth.workload_uniform(scale=scale)
+    subs, vals = to_gpu(X)
+    for mode in range(3):
+        say(f"uniform scale={scale} mode={mode}")
+        (gv_,) = to_gpu(X, vecs[mode])[2:]
+        gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+        check_ttv(X, mode, vecs[mode], gs, gv, F64_TOL, f"uniform mode {mode}")
+
+
+def test_skewed_multilevel_f64():
+    """Zipf-skewed 4-way tensor with duplicates: the heaviest first-level
+    buckets are split again at the next level, in FP64."""
+    P = _api()
+    X, mode, v = synth.workload_zipf(scale=0.004)  # 2e5 nnz
+    X64 = synth.COO(X.subs.astype(np.int64), X.vals.astype(np.float64), X.shape)
+    v64 = v.astype(np.float64)
+    subs, vals, gv_ = to_gpu(X64, v64)
+    say("zipf f64 2e5")
+    gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+    check_ttv(X64, mode, v64, gs, gv, F64_TOL, "zipf f64")
+
+
+def test_compensated_fp32_skewed():
+    P = _api()
+    X, mode, v = synth.workload_zipf(scale=0.004)
+    subs, vals, gv_ = to_gpu(X, v)
+    say("zipf c32 2e5")
+    gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_, out_f64=True)
+    check_ttv(X, mode, v, gs, gv, C32_TOL, "zipf c32")
+    gs2, gv2, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+    assert gv2.dtype.itemsize == 4
+    assert np.array_equal(gs2.cpu().numpy(), gs.cpu().numpy())
+
+
+def test_deterministic():
+    P = _api()
+    X, mode, v = synth.workload_zipf(scale=0.002)
+    subs, vals, gv_ = to_gpu(X, v)
+    a = P.ttv(subs, vals, X.shape, mode, gv_)
+    b = P.ttv(subs, vals, X.shape, mode, gv_)
+    assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
+    assert np.array_equal(a[1].cpu().numpy().view(np.uint32), b[1].cpu().numpy().view(np.uint32))
+
+
+def _hot_key_tensor(seed, nnz=200_000, dtype=np.float64):
+    """3-way 300x50x200 tensor where a few output keys (mode 1 contracted)
+    take most of the nonzeros: one key gets 40%, one 15%, one 6% -- each
+    far beyond one LDS leaf, so they become single-key leaves reduced by
+    several blocks and combined across blocks."""
+    rng = np.random.default_rng(seed)
+    subs = np.stack([rng.integers(0, 300, nnz), rng.integers(0, 50, nnz), rng.integers(0, 200, nnz)], 1)
+    u = rng.random(nnz)
+    subs[u < 0.40, 0], subs[u < 0.40, 2] = 0, 0
+    m = (u >= 0.40) & (u < 0.55)
+    subs[m, 0], subs[m, 2] = 7, 123
+    m = (u >= 0.55) & (u < 0.61)
+    subs[m, 0], subs[m, 2] = 299, 199
+    vals = rng.standard_normal(nnz).astype(dtype)
+    return synth.COO(subs.astype(np.int64), vals, (300, 50, 200))
+
+
+def test_hot_keys_cross_block_f64():
+    P = _api()
+    X = _hot_key_tensor(1)
+    v = np.random.default_rng(2).standard_normal(50)
+    subs, vals, gv_ = to_gpu(X, v)
+    say("hot keys f64")
+    gs, gv, _ = P.ttv(subs, vals, X.shape, 1, gv_)
+    check_ttv(X, 1, v, gs, gv, F64_TOL, "hot keys f64")
+
+
+def test_hot_keys_cross_block_c32():
+    P = _api()
+    X = _hot_key_tensor(3, dtype=np.float32)
+    X = synth.COO(X.subs.astype(np.int32), X.vals, X.shape)
+    v = np.random.default_rng(4).standard_normal(50).astype(np.float32)
+    subs, vals, gv_ = to_gpu(X, v)
+    say("hot keys c32")
+    gs, gv, _ = P.ttv(subs, vals, X.shape, 1, gv_, out_f64=True)
+    check_ttv(X, 1, v, gs, gv, C32_TOL, "hot keys c32")
+
+
+def test_wide_keys_over_32_bits():
+    """5-way tensor whose remaining-mode indices need 52 key bits: the LDS
+    sort runs on 64-bit relative keys."""
+    P = _api()
+    X = synth.tiny(61, 5, (5000, 4000, 3000, 4500, 7), 6000)
+    for mode in (4, 0):
+        v = np.random.default_rng(mode).random(X.shape[mode])
+        subs, vals, gv_ = to_gpu(X, v)
+        info = P.plan_query(subs, vals, X.shape, [mode])
+        assert info.key_bits > 32
+        say(f"wide keys mode={mode} bits={info.key_bits}")
+        gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_)
+        check_ttv(X, mode, v, gs, gv, F64_TOL, "wide")
+
+
+def test_zipf_deeper_levels():
+    """1e6 Zipf nonzeros: heavy first-level buckets split at two more levels."""
+    P = _api()
+    X, mode, v = synth.workload_zipf(scale=0.02)
+    subs, vals, gv_ = to_gpu(X, v)
+    info = P.plan_query(subs, vals, X.shape, [mode])
+    assert info.levels >= 3
+    say("zipf 1e6 c32")
+    gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_, out_f64=True)
+    check_ttv(X, mode, v, gs, gv, C32_TOL, "zipf 1e6")
