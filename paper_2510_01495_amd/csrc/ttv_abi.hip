@@ -96,6 +96,14 @@ int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
     D.shift[i] = sh;
     sh += D.width[i];
   }
+  for (int j = 0; j < TTV_MAX_ORDER; ++j) {
+    D.mshift[j] = -1;
+    D.mwidth[j] = 0;
+  }
+  for (int i = 0; i < nr; ++i) {
+    D.mshift[D.rem[i]] = D.shift[i];
+    D.mwidth[D.rem[i]] = D.width[i];
+  }
   // first digit: expected bucket about 0.6 * kSmall records
   int r1 = 0;
   const double target = 0.6 * kSmall;

@@ -118,6 +118,7 @@ struct FormOps<kF64> {
     return (uint64_t)__double_as_longlong(__longlong_as_double((long long)p) * x);
   }
   static __device__ __forceinline__ Acc shfl_up(Acc a, int d) { return __shfl_up(a, d, 64); }
+  static __device__ __forceinline__ Acc shfl_last(Acc a) { return __shfl(a, 63, 64); }
 };
 
 template <>
@@ -151,6 +152,7 @@ struct FormOps<kC32> {
   static __device__ __forceinline__ Acc shfl_up(Acc a, int d) {
     return C2{__shfl_up(a.s, d, 64), __shfl_up(a.c, d, 64)};
   }
+  static __device__ __forceinline__ Acc shfl_last(Acc a) { return C2{__shfl(a.s, 63, 64), __shfl(a.c, 63, 64)}; }
 };
 
 // Segmented-scan element: `f` marks that a segment head lies inside.
@@ -165,6 +167,67 @@ __device__ __forceinline__ Seg<F> seg_combine(const Seg<F>& a, const Seg<F>& b) 
   r.f = a.f | b.f;
   r.v = b.f ? b.v : FormOps<F>::add(a.v, b.v);
   return r;
+}
+
+// Pointers in the global address space: loads and stores through them are
+// global_* instructions rather than flat ones.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<const T> to_global(const T* p) {
+  return (gptr<const T>)p;
+}
+
+// A record as one 16-byte vector (key, payload) for single load/store
+// instructions in any address space.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// DPP move of a 32-bit value; lanes whose source is outside the pattern (or
+// whose row is masked off) receive 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xf, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp32<CTRL, ROWMASK>((int)(unsigned)b);
+  const int hi = dpp32<CTRL, ROWMASK>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dppf(float v) {
+  return __int_as_float(dpp32<CTRL, ROWMASK>(__float_as_int(v)));
+}
+
+template <int F, int CTRL, int ROWMASK>
+__device__ __forceinline__ Seg<F> seg_dpp_step(const Seg<F>& e) {
+  Seg<F> y;
+  y.f = dpp32<CTRL, ROWMASK>(e.f);
+  if constexpr (F == kF64) {
+    y.v = dpp64<CTRL, ROWMASK>(e.v);
+  } else {
+    y.v.s = dppf<CTRL, ROWMASK>(e.v.s);
+    y.v.c = dppf<CTRL, ROWMASK>(e.v.c);
+  }
+  return seg_combine<F>(y, e);  // y is the identity where the source lane is invalid
+}
+
+// Inclusive segmented scan across the 64 lanes of a wave: row_shr 1/2/4/8
+// within rows of 16, then row_bcast:15 and row_bcast:31 across rows.
+template <int F>
+__device__ __forceinline__ Seg<F> wave_seg_scan(Seg<F> e) {
+  e = seg_dpp_step<F, 0x111, 0xf>(e);
+  e = seg_dpp_step<F, 0x112, 0xf>(e);
+  e = seg_dpp_step<F, 0x114, 0xf>(e);
+  e = seg_dpp_step<F, 0x118, 0xf>(e);
+  e = seg_dpp_step<F, 0x142, 0xa>(e);
+  e = seg_dpp_step<F, 0x143, 0xc>(e);
+  return e;
 }
 
 // Index loads from either index type.

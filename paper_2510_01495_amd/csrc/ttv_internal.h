@@ -70,6 +70,8 @@ struct TDesc {
   int32_t shift[kMaxOrder];     // bit position of each remaining mode's field
   int32_t width[kMaxOrder];
   int32_t con[kMaxOrder];       // contracted modes, ascending
+  int32_t mshift[kMaxOrder];    // per mode: key shift of a remaining mode, -1 if contracted
+  int32_t mwidth[kMaxOrder];    // per mode: key bits of a remaining mode
   int32_t r1;                   // digit bits of the first level
   int32_t ndig_modes;           // leading remaining modes that overlap the first digit
   int32_t out_f64;              // compensated form writes FP64 values

@@ -67,6 +67,28 @@ __device__ __forceinline__ long long field(long long x, int width) {
   return x & (long long)((width >= 63) ? ~0ull >> 1 : ((1ull << width) - 1ull));
 }
 
+#ifdef TTV_PHASE_PROFILE
+// Build-time option for kernel phase timing (wall clock, 100 MHz ticks).
+__device__ unsigned long long g_phase[16];
+#define TTV_PHASE_DECL unsigned long long ph_t = wall_clock64();
+#define TTV_PHASE(i)                                             \
+  if (threadIdx.x == 0) {                                        \
+    const unsigned long long ph_n = wall_clock64();              \
+    atomicAdd(&g_phase[i], ph_n - ph_t);                         \
+    ph_t = ph_n;                                                 \
+  }
+extern "C" int ttv_debug_phases(unsigned long long* out) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase));
+}
+extern "C" int ttv_debug_phases_reset() {
+  unsigned long long z[16] = {0};
+  return (int)hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z));
+}
+#else
+#define TTV_PHASE_DECL
+#define TTV_PHASE(i)
+#endif
+
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagInc = 2ull << 62;
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
@@ -77,36 +99,94 @@ constexpr int kBitmapWordsPerBlock = 8192;  // 256 threads x 32 words
 // first remaining mode most significant; payload = value times the vector
 // entries of the contracted modes (ascending), or the nonzero's index.
 // ---------------------------------------------------------------------------
-template <typename IdxT, int F, int PM>
-__device__ __forceinline__ void make_record(const TDesc& D, long long e, Ctrl* C, uint64_t& key,
-                                            uint64_t& pay) {
+// What a tile needs to read nonzeros of one tensor, staged in LDS once per
+// tile (descriptor fields read from global memory would be re-fetched after
+// every store).
+template <typename IdxT, int F>
+struct RawSrc {
+  using In = typename FormOps<F>::In;
+  const IdxT* subs;
+  const In* vals;
+  long long se;
+  int order;
+  int validate;
+  const In* vec[kMaxOrder];
+  long long sj[kMaxOrder];
+  long long dim[kMaxOrder];
+  int shift[kMaxOrder];  // key shift of a remaining mode, -1 if contracted
+  int width[kMaxOrder];
+  __device__ __forceinline__ void set(const TDesc& D) {
+    subs = static_cast<const IdxT*>(D.subs);
+    vals = static_cast<const In*>(D.vals);
+    se = D.stride_e;
+    order = D.order;
+    validate = D.validate;
+    for (int m = 0; m < kMaxOrder; ++m) {
+      vec[m] = static_cast<const In*>(D.vec[m]);
+      sj[m] = (long long)m * D.stride_j;
+      dim[m] = D.dims[m];
+      shift[m] = D.mshift[m];
+      width[m] = D.mwidth[m];
+    }
+  }
+};
+
+// One round of IPT records per lane: item j of this lane is nonzero
+// e0 + j*64 (valid while j*64 < n_left).  Loads are issued per mode for all
+// items at once.
+template <typename IdxT, int F, int PM, int IPT>
+__device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e0, long long n_left, Ctrl* C,
+                                           uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
   using FO = FormOps<F>;
   using In = typename FO::In;
-  uint64_t k = 0;
-  for (int i = 0; i < D.nrem; ++i) {
-    long long x = ld_idx<IdxT>(D, e, D.rem[i]);
-    if (D.validate && (x < 0 || x >= D.dims[D.rem[i]])) {
-      set_error(C, TTV_E_INDEX);
-      x = 0;
+  const gptr<const In> vals = to_global(S.vals);
+  const gptr<const IdxT> subs = to_global(S.subs);
+  const long long se = S.se;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    key[j] = 0;
+    pay[j] = 0;
+    if ((long long)j * 64 < n_left) {
+      if (PM == kPipeSegMap)
+        pay[j] = (uint64_t)(e0 + (long long)j * 64);
+      else
+        pay[j] = FO::start_prod(vals[e0 + (long long)j * 64]);
     }
-    k |= (uint64_t)field(x, D.width[i]) << D.shift[i];
   }
-  key = k;
-  if (PM == kPipeSegMap) {
-    pay = (uint64_t)e;
-    return;
-  }
-  uint64_t p = FO::start_prod(static_cast<const In*>(D.vals)[e]);
-  for (int c = 0; c < D.ncon; ++c) {
-    const int m = D.con[c];
-    long long x = ld_idx<IdxT>(D, e, m);
-    if (D.validate && (x < 0 || x >= D.dims[m])) {
-      set_error(C, TTV_E_INDEX);
-      x = 0;
+  const int order = S.order;
+  const bool validate = S.validate != 0;
+  for (int m = 0; m < order; ++m) {
+    const int sh = S.shift[m];
+    if (PM == kPipeSegMap && sh < 0) continue;
+    const long long sj = S.sj[m];
+    long long x[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      x[j] = 0;
+      if ((long long)j * 64 < n_left) x[j] = (long long)subs[(e0 + (long long)j * 64) * se + sj];
     }
-    p = FO::mul_prod(p, static_cast<const In*>(D.vec[m])[x]);
+    if (validate) {
+      const long long dim = S.dim[m];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j)
+        if ((long long)j * 64 < n_left && (x[j] < 0 || x[j] >= dim)) {
+          set_error(C, TTV_E_INDEX);
+          x[j] = 0;
+        }
+    }
+    if (sh >= 0) {
+      const int wd = S.width[m];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) key[j] |= (uint64_t)field(x[j], wd) << sh;
+    } else {
+      const gptr<const In> vec = to_global(S.vec[m]);
+      In g[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) g[j] = ((long long)j * 64 < n_left) ? vec[x[j]] : (In)0;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[j]);
+    }
   }
-  pay = p;
 }
 
 // ---------------------------------------------------------------------------
@@ -195,6 +275,7 @@ __device__ __forceinline__ void hist_add(unsigned* hist, unsigned d, bool valid)
 // ---------------------------------------------------------------------------
 template <typename IdxT>
 __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
+  constexpr int IPT = 16;
   __shared__ unsigned hist[kNDig];
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
@@ -202,6 +283,8 @@ __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
   const Job* jobs = W.jobs(level);
   const int* tj = W.tiles(level);
   unsigned* table = W.table();
+  const int w = threadIdx.x >> 6;
+  const unsigned ln = lane_id();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Job J = jobs[tj[t]];
     const int nd = 1 << J.r;
@@ -210,31 +293,37 @@ __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
     __syncthreads();
     const long long b = (long long)(t - J.tile0) * T;
     const long long n = (J.size - b < (long long)T) ? J.size - b : (long long)T;
-    if (J.src == kSrcRaw) {
-      const TDesc& D = W.desc()[J.tensor];
-      const long long off = J.start - D.base + b;
-      for (long long rb = 0; rb < n; rb += 256) {
-        const long long i = rb + threadIdx.x;
-        const bool valid = i < n;
-        unsigned d = 0;
-        if (valid) {
-          uint64_t key = 0;
-          for (int m = 0; m < D.ndig_modes; ++m) {
-            long long x = ld_idx<IdxT>(D, off + i, D.rem[m]);
-            if (D.validate && (x < 0 || x >= D.dims[D.rem[m]])) x = 0;
-            key |= (uint64_t)field(x, D.width[m]) << D.shift[m];
+    // rounds of 256*IPT records; wave w takes a contiguous 64*IPT slice
+    for (long long rb = 0; rb < n; rb += 256 * IPT) {
+      const long long i0 = rb + (long long)w * 64 * IPT + ln;
+      uint64_t key[IPT];
+      if (J.src == kSrcRaw) {
+        const TDesc& D = W.desc()[J.tensor];
+        const IdxT* subs = static_cast<const IdxT*>(D.subs);
+        const long long e0 = J.start - D.base + b + i0;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) key[j] = 0;
+        for (int q = 0; q < D.ndig_modes; ++q) {
+          const int m = D.rem[q];
+          long long x[IPT];
+#pragma unroll
+          for (int j = 0; j < IPT; ++j)
+            x[j] = (i0 + j * 64 < n) ? (long long)subs[(e0 + j * 64) * D.stride_e + (long long)m * D.stride_j] : 0;
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            if (D.validate && (x[j] < 0 || x[j] >= D.dims[m])) x[j] = 0;
+            key[j] |= (uint64_t)field(x[j], D.width[q]) << D.shift[q];
           }
-          d = (unsigned)(key >> J.shift) & mask;
         }
-        hist_add(hist, d, valid);
+      } else {
+        const Rec* R = W.rec(J.src) + J.start + b;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) key[j] = (i0 + j * 64 < n) ? R[i0 + j * 64].key : 0;
       }
-    } else {
-      const Rec* R = W.rec(J.src) + J.start + b;
-      for (long long rb = 0; rb < n; rb += 256) {
-        const long long i = rb + threadIdx.x;
-        const bool valid = i < n;
-        const unsigned d = valid ? (unsigned)(R[i].key >> J.shift) & mask : 0u;
-        hist_add(hist, d, valid);
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const bool valid = i0 + j * 64 < n;
+        hist_add(hist, (unsigned)(key[j] >> J.shift) & mask, valid);
       }
     }
     __syncthreads();
@@ -511,7 +600,9 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
   constexpr int RW = 64 * IPT;            // records per wave per round
   constexpr int RN = kScatterThreads * IPT;
   __shared__ unsigned cursor[kNDig];
-  __shared__ unsigned short wcnt[4][kNDig];
+  __shared__ unsigned wcnt32[4][kNDig / 2];  // per-wave u16 counters, two per word
+  __shared__ RawSrc<IdxT, F> rsrc;
+  auto wcnt = [&](int q, unsigned d) -> unsigned { return (wcnt32[q][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int ntiles = clampi(C->ntiles[level], W.L.tcap);
@@ -526,50 +617,63 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
     const unsigned mask = (unsigned)nd - 1u;
     const unsigned* row = W.table() + (size_t)t * kNDig;
     const unsigned* st = W.starts() + (size_t)jid * kNDig;
-    for (int i = threadIdx.x; i < nd; i += kScatterThreads) {
-      cursor[i] = st[i] + row[i];
-      wcnt[0][i] = 0;
-      wcnt[1][i] = 0;
-      wcnt[2][i] = 0;
-      wcnt[3][i] = 0;
+    for (int i = threadIdx.x; i < nd; i += kScatterThreads) cursor[i] = st[i] + row[i];
+    for (int i = threadIdx.x; i < kNDig / 2; i += kScatterThreads) {
+      wcnt32[0][i] = 0;
+      wcnt32[1][i] = 0;
+      wcnt32[2][i] = 0;
+      wcnt32[3][i] = 0;
     }
     __syncthreads();
     const long long b = (long long)(t - J.tile0) * T;
     const long long n = (J.size - b < (long long)T) ? J.size - b : (long long)T;
     Rec* dst = W.rec(dst_of(level)) + J.start;
-    const Rec* srcR = (J.src == kSrcRaw) ? nullptr : W.rec(J.src) + J.start + b;
+    const gptr<const u64x2> srcR = (J.src == kSrcRaw)
+                                       ? (gptr<const u64x2>)nullptr
+                                       : to_global((const u64x2*)W.rec(J.src)) + J.start + b;
     const TDesc* Dp = W.desc() + J.tensor;
     const long long roff = J.start - Dp->base + b;
+    if (J.src == kSrcRaw) {
+      if (threadIdx.x == 0) rsrc.set(*Dp);
+      __syncthreads();
+    }
+    gptr<u64x2> gdst = to_global((u64x2*)dst);
     for (long long rb = 0; rb < n; rb += RN) {
       uint64_t key[IPT], pay[IPT];
       unsigned dg[IPT], rk[IPT];
       bool first[IPT];
+      {
+        const long long i0 = rb + (long long)w * RW + ln;
+        if (srcR) {
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const long long i = rb + (long long)w * RW + j * 64 + ln;
-        if (i < n) {
-          if (srcR) {
-            const Rec r = srcR[i];
-            key[j] = r.key;
-            pay[j] = r.pay;
-          } else {
-            make_record<IdxT, F, PM>(*Dp, roff + i, C, key[j], pay[j]);
+          for (int j = 0; j < IPT; ++j) {
+            key[j] = 0;
+            pay[j] = 0;
+            if (i0 + j * 64 < n) {
+              const u64x2 r = srcR[i0 + j * 64];
+              key[j] = r.x;
+              pay[j] = r.y;
+            }
           }
+        } else {
+          load_round<IdxT, F, PM, IPT>(rsrc, roff + i0, n - i0, C, key, pay);
         }
       }
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
         const long long i = rb + (long long)w * RW + j * 64 + ln;
         const bool valid = i < n;
-        const uint64_t vm = ballot(valid);
         dg[j] = valid ? (unsigned)(key[j] >> J.shift) & mask : 0u;
-        const uint64_t peers = match_digit(dg[j], J.r, vm);
-        unsigned old = 0;
-        if (valid) old = wcnt[w][dg[j]];
-        const unsigned below = count_below(peers);
-        rk[j] = old + below;
-        first[j] = valid && old == 0 && below == 0;
-        if (valid) wcnt[w][dg[j]] = (unsigned short)(old + (unsigned)__popcll(peers));
+        rk[j] = 0;
+        first[j] = false;
+        if (valid) {
+          // stable rank within the wave: same-address lanes of one LDS
+          // atomic are served in lane order
+          const unsigned hs = (dg[j] & 1u) * 16u;
+          const unsigned old = (atomicAdd(&wcnt32[w][dg[j] >> 1], 1u << hs) >> hs) & 0xffffu;
+          rk[j] = old;
+          first[j] = old == 0;
+        }
       }
       __syncthreads();
       bool up[IPT];
@@ -580,12 +684,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
         if (i < n) {
           const unsigned d = dg[j];
           unsigned lower = 0;
-          for (int q = 0; q < w; ++q) lower += wcnt[q][d];
+          for (int q = 0; q < w; ++q) lower += wcnt(q, d);
           const unsigned pos = cursor[d] + lower + rk[j];
-          Rec r;
-          r.key = key[j];
-          r.pay = pay[j];
-          dst[pos] = r;
+          u64x2 r;
+          r.x = key[j];
+          r.y = pay[j];
+          gdst[pos] = r;
           up[j] = first[j] && lower == 0;
         }
       }
@@ -594,13 +698,13 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
       for (int j = 0; j < IPT; ++j) {
         if (up[j]) {
           const unsigned d = dg[j];
-          cursor[d] += (unsigned)wcnt[0][d] + wcnt[1][d] + wcnt[2][d] + wcnt[3][d];
+          cursor[d] += wcnt(0, d) + wcnt(1, d) + wcnt(2, d) + wcnt(3, d);
         }
       }
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < IPT; ++j)
-        if (first[j]) wcnt[w][dg[j]] = 0;
+        if (first[j]) atomicAnd(&wcnt32[w][dg[j] >> 1], ~(0xffffu << ((dg[j] & 1u) * 16u)));
     }
     __syncthreads();
   }
@@ -701,83 +805,118 @@ __global__ __launch_bounds__(256) void k_rank(WsView W) {
 // ---------------------------------------------------------------------------
 // finish
 // ---------------------------------------------------------------------------
-__device__ long long lookback(unsigned long long* S, int r, int spin_limit, Ctrl* C) {
+__device__ __forceinline__ void publish(unsigned long long* S, int r, unsigned long long v) {
+  __hip_atomic_store(&S[r], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back by one wave: 64 predecessors per step; the nearest
+// inclusive prefix ends the walk, the aggregates after it are added.
+__device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit, Ctrl* C) {
+  const unsigned ln = lane_id();
   long long prefix = 0;
-  for (int j = r - 1; j >= 0; --j) {
-    unsigned long long s;
-    int spins = 0;
-    for (;;) {
-      s = __hip_atomic_load(&S[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      if (s >> 62) break;
-      if (++spins > spin_limit) {
-        set_error(C, TTV_E_DEVICE);
-        return prefix;
+  for (int base = r - 1;; base -= 64) {
+    const int j = base - (int)ln;
+    unsigned long long s = kFlagInc;  // before the first leaf: an inclusive prefix of 0
+    if (j >= 0) {
+      int spins = 0;
+      for (;;) {
+        s = __hip_atomic_load(&S[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s >> 62) break;
+        if (++spins > spin_limit) {
+          set_error(C, TTV_E_DEVICE);
+          s = kFlagInc;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      __builtin_amdgcn_s_sleep(2);
     }
-    prefix += (long long)(s & kValMask);
-    if ((s >> 62) == 2) break;
+    const uint64_t pm = ballot((s >> 62) == 2);
+    const int stop = pm ? __ffsll((long long)pm) - 1 : 63;
+    long long v = ((int)ln <= stop) ? (long long)(s & kValMask) : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    prefix += v;
+    if (pm) break;
   }
   return prefix;
 }
 
-__device__ __forceinline__ void publish(unsigned long long* S, int r, unsigned long long v) {
-  __hip_atomic_store(&S[r], v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename IdxT>
-__device__ __forceinline__ void write_coords(const TDesc& D, long long row, uint64_t key) {
-  IdxT* o = static_cast<IdxT*>(D.out_subs) + row * D.nrem;
-  for (int i = 0; i < D.nrem; ++i) {
-    const uint64_t m = D.width[i] >= 64 ? ~0ull : ((1ull << D.width[i]) - 1ull);
-    o[i] = (IdxT)((key >> D.shift[i]) & m);
+// Output pointers and key layout of one tensor, held in registers while a
+// leaf is written (the descriptor itself lives in global memory).
+template <typename IdxT, int F>
+struct OutInfo {
+  gptr<IdxT> subs;
+  gptr<double> v64;
+  gptr<float> v32;
+  int nrem;
+  int f64out;
+  int shift[kMaxOrder];
+  unsigned long long mask[kMaxOrder];
+  __device__ __forceinline__ void load(const TDesc& D) {
+    subs = to_global(static_cast<IdxT*>(D.out_subs));
+    v64 = to_global(static_cast<double*>(D.out_vals));
+    v32 = to_global(static_cast<float*>(D.out_vals));
+    nrem = D.nrem;
+    f64out = (F == kF64) || D.out_f64;
+#pragma unroll
+    for (int i = 0; i < kMaxOrder; ++i) {
+      shift[i] = D.shift[i];
+      mask[i] = D.width[i] >= 64 ? ~0ull : ((1ull << D.width[i]) - 1ull);
+    }
   }
-}
-
-template <int F>
-__device__ __forceinline__ void write_value(const TDesc& D, long long row, double v64,
-                                            const typename FormOps<F>::Acc& a) {
-  if (F == kF64) {
-    static_cast<double*>(D.out_vals)[row] = v64;
-  } else if (D.out_f64) {
-    static_cast<double*>(D.out_vals)[row] = v64;
-  } else {
-    static_cast<float*>(D.out_vals)[row] = (float)v64;
+  __device__ __forceinline__ void write(long long row, uint64_t key, double v) const {
+    gptr<IdxT> o = subs + row * nrem;
+#pragma unroll
+    for (int i = 0; i < kMaxOrder; ++i)
+      if (i < nrem) o[i] = (IdxT)((key >> shift[i]) & mask[i]);
+    if (f64out)
+      v64[row] = v;
+    else
+      v32[row] = (float)v;
   }
-}
+};
 
 template <typename IdxT, int F, int PM>
-__global__ __launch_bounds__(kFinishThreads) void k_finish(WsView W, int spin_limit) {
+__global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin_limit) {
   using FO = FormOps<F>;
   using Acc = typename FO::Acc;
   constexpr int NT = kFinishThreads;
   constexpr int IPT = kFinishIPT;
   constexpr int NW = NT / 64;
+  constexpr int MAXD = 9;  // widest LDS digit
   __shared__ unsigned sk[kCap];
   __shared__ unsigned short si[kCap];
-  __shared__ unsigned cnt[NW * 256];
+  __shared__ unsigned cnt[NW << MAXD];
   __shared__ unsigned wsum[NW];
   __shared__ Seg<F> wagg[NW];
   __shared__ int s_ticket;
   __shared__ long long s_prefix;
+  __shared__ OutInfo<IdxT, F> sO;
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int nleaves = clampi(C->nleaves, W.L.lcap);
   unsigned long long* S = W.status();
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
+  TTV_PHASE_DECL
   for (;;) {
     if (tid == 0) s_ticket = atomicAdd(&C->ticket, 1);
     __syncthreads();
     const int r = s_ticket;
     if (r >= nleaves) break;
+    TTV_PHASE(0)
     const Leaf Lf = W.ordered()[r];
     const TDesc& D = W.desc()[Lf.tensor];
     const bool first = Lf.start == D.base;
     const bool last = Lf.start + Lf.size == D.base + D.nnz;
-    const Rec* R = W.rec(Lf.src) + Lf.start;
-    const long long n = Lf.size;
-    if (Lf.kind != kLeafPure && (n > kCap || n <= 0)) {  // excluded by classification
+    gptr<long long> out_nnz = to_global(D.out_nnz);
+    gptr<int32_t> seg_out = to_global(D.seg_out);
+    if (tid == 0) sO.load(D);
+    __syncthreads();
+    const OutInfo<IdxT, F>& O = sO;
+    const gptr<const Rec> R = to_global(static_cast<const Rec*>(W.rec(Lf.src))) + Lf.start;
+    const int n = (int)(Lf.size < (long long)kCap ? Lf.size : (long long)kCap);
+    if (Lf.kind != kLeafPure && (Lf.size > kCap || Lf.size <= 0)) {  // excluded by classification
       if (tid == 0) {
         set_error(C, TTV_E_DEVICE);
         publish(S, r, kFlagInc);
@@ -786,98 +925,100 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(WsView W, int spin_li
       continue;
     }
     if (Lf.kind == kLeafPure) {
-      if (tid == 0) {
-        publish(S, r, (first ? kFlagInc : kFlagAgg) | 1ull);
-        double v = 0.0;
-        const double* P = W.partials() + Lf.ptile0;
-        for (int k = 0; k < Lf.nptiles; ++k) v += P[k];
-        const long long prefix = first ? 0 : lookback(S, r, spin_limit, C);
-        if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + 1));
-        s_prefix = prefix;
-        if (PM == kPipeTTV) {
-          write_coords<IdxT>(D, prefix, Lf.base);
-          write_value<F>(D, prefix, v, FO::zero());
+      if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | 1ull);
+      if (w == 0) {
+        const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
+        if (ln == 0) {
+          if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + 1));
+          s_prefix = prefix;
+          double v = 0.0;
+          const double* P = W.partials() + Lf.ptile0;
+          for (int k = 0; k < Lf.nptiles; ++k) v += P[k];
+          if (PM == kPipeTTV) O.write(prefix, Lf.base, v);
+          if (last && out_nnz) *out_nnz = prefix + 1;
         }
-        if (last && D.out_nnz) *D.out_nnz = prefix + 1;
       }
       if (PM == kPipeSegMap) {
         __syncthreads();
         const long long row = s_prefix;
-        for (long long i = tid; i < n; i += NT) D.seg_out[(long long)R[i].pay] = (int32_t)row;
+        for (long long i = tid; i < Lf.size; i += NT) seg_out[(long long)R[i].pay] = (int32_t)row;
       }
       __syncthreads();
       continue;
     }
-    // ---- load relative keys (wave-striped) ----
+    // ---- LDS radix sort of the relative keys.  Wave w holds the contiguous
+    // positions [w*64*nj, (w+1)*64*nj), item j of a lane is position
+    // w*64*nj + j*64 + lane: ranking in (wave, item, lane) order is ranking
+    // in position order, which keeps every pass stable. ----
     const bool wide = Lf.bits > 32;
+    const int nj = (n + 64 * NW - 1) / (64 * NW);
     unsigned k[IPT];
-    unsigned short ix[IPT];
+    unsigned ix[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-      const int i = w * (64 * IPT) + j * 64 + (int)ln;
+      const int i = w * 64 * nj + j * 64 + (int)ln;
+      ix[j] = (unsigned)i;
       k[j] = 0;
-      ix[j] = (unsigned short)i;
-      if (i < n) k[j] = (unsigned)(R[i].key - Lf.base);
+      if (j < nj) k[j] = (unsigned)(R[i < n ? i : n - 1].key - Lf.base);
     }
-    const int npass = (Lf.bits + kSortDigit - 1) / kSortDigit;
+    TTV_PHASE(1)
+    const int npass = (Lf.bits + MAXD - 1) / MAXD;
+    const int dw = npass ? (Lf.bits + npass - 1) / npass : 0;
+    const int nb = 1 << dw;
+    const unsigned dmask = (unsigned)nb - 1u;
     for (int pass = 0; pass < npass; ++pass) {
-      const int sh = pass * kSortDigit;
-      for (int q = tid; q < NW * 256; q += NT) cnt[q] = 0u;
+      const int sh = pass * dw;
+      for (int q = tid; q < NW * nb; q += NT) cnt[q] = 0u;
       __syncthreads();
-      unsigned dg[IPT], rk[IPT];
+      unsigned rk[IPT];
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const int i = w * (64 * IPT) + j * 64 + (int)ln;
-        const bool valid = i < n;
-        const uint64_t vm = ballot(valid);
-        unsigned d = 0;
-        if (valid) {
-          if (wide)
-            d = (unsigned)(((R[ix[j]].key - Lf.base) >> sh) & 255u);
-          else
-            d = (k[j] >> sh) & 255u;
+        const int i = w * 64 * nj + j * 64 + (int)ln;
+        // stable rank: one LDS atomic per item on the wave's own counters
+        // (same-address lanes of one instruction are served in lane order)
+        rk[j] = 0;
+        if (j < nj && i < n) {
+          const unsigned d = wide ? (unsigned)(((R[ix[j]].key - Lf.base) >> sh) & dmask) : (k[j] >> sh) & dmask;
+          rk[j] = atomicAdd(&cnt[w * nb + d], 1u);
         }
-        dg[j] = d;
-        const uint64_t peers = match_digit(d, kSortDigit, vm);
-        unsigned old = 0;
-        if (valid) old = cnt[w * 256 + d];
-        rk[j] = old + count_below(peers);
-        if (valid) cnt[w * 256 + d] = old + (unsigned)__popcll(peers);
       }
       __syncthreads();
       {  // exclusive scan of the counters in (digit, wave) order
-        unsigned v[4], s = 0;
+        const int E = NW * nb;
+        const int ept = (E + NT - 1) / NT;
+        unsigned v[8], s = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid * 4 + q;
-          v[q] = cnt[(e & 7) * 256 + (e >> 3)];
+        for (int q = 0; q < 8; ++q) {
+          const int e = tid * ept + q;
+          v[q] = (q < ept && e < E) ? cnt[(e % NW) * nb + e / NW] : 0u;
           s += v[q];
         }
         unsigned tot;
         unsigned ex = block_excl_scan<NT>(s, wsum, tot);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid * 4 + q;
-          cnt[(e & 7) * 256 + (e >> 3)] = ex;
+        for (int q = 0; q < 8; ++q) {
+          const int e = tid * ept + q;
+          if (q < ept && e < E) cnt[(e % NW) * nb + e / NW] = ex;
           ex += v[q];
         }
       }
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const int i = w * (64 * IPT) + j * 64 + (int)ln;
-        if (i < n) {
-          const unsigned dest = cnt[w * 256 + dg[j]] + rk[j];
+        const int i = w * 64 * nj + j * 64 + (int)ln;
+        if (j < nj && i < n) {
+          const unsigned d = wide ? (unsigned)(((R[ix[j]].key - Lf.base) >> sh) & dmask) : (k[j] >> sh) & dmask;
+          const unsigned dest = cnt[w * nb + d] + rk[j];
           sk[dest] = k[j];
-          si[dest] = ix[j];
+          si[dest] = (unsigned short)ix[j];
         }
       }
       __syncthreads();
       if (pass + 1 < npass) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-          const int i = w * (64 * IPT) + j * 64 + (int)ln;
-          if (i < n) {
+          const int i = w * 64 * nj + j * 64 + (int)ln;
+          if (j < nj && i < n) {
             k[j] = sk[i];
             ix[j] = si[i];
           }
@@ -888,131 +1029,138 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(WsView W, int spin_li
     if (npass == 0) {
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const int i = w * (64 * IPT) + j * 64 + (int)ln;
-        if (i < n) {
+        const int i = w * 64 * nj + j * 64 + (int)ln;
+        if (j < nj && i < n) {
           sk[i] = k[j];
-          si[i] = ix[j];
+          si[i] = (unsigned short)ix[j];
         }
       }
       __syncthreads();
     }
-    // ---- segmented reduction over the sorted order (blocked) ----
-    const int p0 = tid * IPT;
-    uint64_t fk[IPT];  // full keys (wide) or relative keys
-    bool head[IPT];
-    unsigned hc = 0;
+    TTV_PHASE(2)
+    // ---- heads over the sorted order.  Wave w owns positions
+    // [w*64*IPT, (w+1)*64*IPT) in IPT rounds of 64 consecutive positions
+    // (lane-striped), so the output rows a round writes are contiguous. ----
+    const int pw = w * 64 * nj;
+    uint64_t hm[IPT];
+    unsigned whc = 0;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-      const int p = p0 + j;
-      head[j] = false;
-      fk[j] = 0;
-      if (p < n) {
-        fk[j] = wide ? R[si[p]].key : (uint64_t)sk[p];
+      const int p = pw + j * 64 + (int)ln;
+      bool hd = false;
+      if (j < nj && p < n) {
         if (p == 0) {
-          head[j] = true;
+          hd = true;
+        } else if (wide) {
+          hd = R[si[p]].key != R[si[p - 1]].key;
         } else {
-          const uint64_t pk = (j > 0) ? fk[j - 1] : (wide ? R[si[p - 1]].key : (uint64_t)sk[p - 1]);
-          head[j] = pk != fk[j];
-        }
-        hc += head[j] ? 1u : 0u;
-      }
-    }
-    unsigned u;
-    const unsigned hb = block_excl_scan<NT>(hc, wsum, u);
-    if (tid == 0 && !first) publish(S, r, kFlagAgg | (unsigned long long)u);
-    if (tid == 0 && first) publish(S, r, kFlagInc | (unsigned long long)u);
-    Acc val[IPT];
-    Seg<F> agg;
-    agg.f = 0;
-    agg.v = FO::zero();
-    uint64_t pay[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      const int p = p0 + j;
-      pay[j] = 0;
-      if (p < n) {
-        pay[j] = R[si[p]].pay;
-        if (PM == kPipeTTV) {
-          const Acc x = FO::from_pay(pay[j]);
-          if (head[j]) {
-            agg.v = x;
-            agg.f = 1;
-          } else {
-            agg.v = FO::add(agg.v, x);
-          }
-          val[j] = agg.v;
+          hd = sk[p] != sk[p - 1];
         }
       }
+      hm[j] = ballot(hd);
+      whc += (unsigned)__popcll(hm[j]);
     }
-    Seg<F> carry;
-    carry.f = 0;
-    carry.v = FO::zero();
-    if (PM == kPipeTTV) {
-      // exclusive segmented scan of the thread aggregates
-      Seg<F> inc = agg;
+    if (ln == 0) wsum[w] = whc;
+    __syncthreads();
+    unsigned hbw = 0, u = 0;
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        Seg<F> y;
-        y.v = FO::shfl_up(inc.v, o);
-        y.f = __shfl_up(inc.f, o, 64);
-        if ((int)ln >= o) inc = seg_combine<F>(y, inc);
-      }
-      Seg<F> ex;
-      ex.v = FO::shfl_up(inc.v, 1);
-      ex.f = __shfl_up(inc.f, 1, 64);
+    for (int q = 0; q < NW; ++q) {
+      const unsigned c = wsum[q];
+      hbw += (q < w) ? c : 0u;
+      u += c;
+    }
+    if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);
+    // wave 0 resolves this leaf's output offset while the others gather payloads
+    if (w == 0) {
+      const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
       if (ln == 0) {
-        ex.f = 0;
-        ex.v = FO::zero();
+        if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u));
+        s_prefix = prefix;
+        if (last && out_nnz) *out_nnz = prefix + u;
       }
-      if (ln == 63) wagg[w] = inc;
-      __syncthreads();
-      Seg<F> wc;
-      wc.f = 0;
-      wc.v = FO::zero();
-      for (int q = 0; q < w; ++q) wc = seg_combine<F>(wc, wagg[q]);
-      carry = seg_combine<F>(wc, ex);
     }
-    if (tid == 0) {
-      const long long prefix = first ? 0 : lookback(S, r, spin_limit, C);
-      if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u));
-      s_prefix = prefix;
-      if (last && D.out_nnz) *D.out_nnz = prefix + u;
+    TTV_PHASE(3)
+    // ---- payloads and the segmented scan (rounds within the wave) ----
+    Acc val[IPT];
+    if (PM == kPipeTTV) {
+      uint64_t pay[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int p = pw + j * 64 + (int)ln;
+        pay[j] = 0;
+        if (j < nj) pay[j] = R[si[p < n ? p : n - 1]].pay;
+      }
+      Acc c = FO::zero();  // value of the segment open at the end of the previous round
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        if (j >= nj) continue;
+        const bool hd = (hm[j] >> ln) & 1ull;
+        Seg<F> e;
+        e.f = hd ? 1 : 0;
+        e.v = FO::from_pay(pay[j]);
+        e = wave_seg_scan<F>(e);
+        // lanes before the round's first head continue the open segment
+        val[j] = e.f ? e.v : FO::add(c, e.v);
+        c = FO::shfl_last(val[j]);
+      }
+      if (ln == 0) {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) any = any || hm[j] != 0;
+        wagg[w].f = any ? 1 : 0;
+        wagg[w].v = c;
+      }
     }
     __syncthreads();
+    if (PM == kPipeTTV) {
+      // the segment open at the start of this wave continues from earlier waves
+      Seg<F> cw;
+      cw.f = 0;
+      cw.v = FO::zero();
+      for (int q = 0; q < w; ++q) cw = seg_combine<F>(cw, wagg[q]);
+      bool lead = true;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        if (j >= nj) continue;
+        const uint64_t upto = hm[j] & (~0ull >> (63 - ln));  // heads at lanes <= this one
+        const bool my_lead = lead && upto == 0;
+        if (my_lead) val[j] = FO::add(cw.v, val[j]);
+        lead = lead && hm[j] == 0;
+      }
+    }
+    TTV_PHASE(4)
+    __syncthreads();
+    TTV_PHASE(5)
     const long long prefix = s_prefix;
-    // ---- write ----
-    unsigned lh = 0;
-    bool seen = false;
+    // ---- write (consecutive lanes -> consecutive output rows) ----
+    unsigned hrun = hbw;  // heads before this round
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-      const int p = p0 + j;
-      if (p >= n) continue;
-      if (head[j]) {
-        ++lh;
-        seen = true;
+      if (j >= nj) continue;
+      const int p = pw + j * 64 + (int)ln;
+      const unsigned upto = (unsigned)__popcll(hm[j] & (~0ull >> (63 - ln)));
+      if (p < n) {
+        const long long rowi = prefix + hrun + upto - 1;
+        if (PM == kPipeSegMap) {
+          seg_out[(long long)R[si[p]].pay] = (int32_t)rowi;
+        } else {
+          bool end;
+          if (p == n - 1)
+            end = true;
+          else if (wide)
+            end = R[si[p + 1]].key != R[si[p]].key;
+          else
+            end = sk[p + 1] != sk[p];
+          if (end) {
+            const uint64_t key = wide ? R[si[p]].key : Lf.base + sk[p];
+            O.write(rowi, key, FO::to_f64(val[j]));
+          }
+        }
       }
-      const long long rowi = prefix + hb + lh - 1;
-      if (PM == kPipeSegMap) {
-        D.seg_out[(long long)pay[j]] = (int32_t)rowi;
-        continue;
-      }
-      bool end;
-      if (p == n - 1) {
-        end = true;
-      } else if (j + 1 < IPT) {
-        end = head[j + 1];
-      } else {
-        const uint64_t nk = wide ? R[si[p + 1]].key : (uint64_t)sk[p + 1];
-        end = nk != fk[j];
-      }
-      if (end) {
-        const Acc a = seen ? val[j] : FO::add(carry.v, val[j]);
-        const uint64_t key = wide ? fk[j] : Lf.base + fk[j];
-        write_coords<IdxT>(D, rowi, key);
-        write_value<F>(D, rowi, FO::to_f64(a), a);
-      }
+      hrun += (unsigned)__popcll(hm[j]);
     }
     __syncthreads();
+    TTV_PHASE(6)
   }
 }
 
