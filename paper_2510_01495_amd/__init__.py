@@ -7,6 +7,18 @@ only supplies device memory and streams.
 """
 
 from . import _lib  # noqa: F401
-from .api import TTVOp, coo_desc, plan_query, ttv, ttv_multi  # noqa: F401
+from .api import (  # noqa: F401
+    AllButOp,
+    TTVAllButFunction,
+    TTVFunction,
+    TTVOp,
+    coo_desc,
+    plan_query,
+    ttv,
+    ttv_allbut,
+    ttv_backward,
+    ttv_multi,
+)
 
-__all__ = ["TTVOp", "coo_desc", "plan_query", "ttv", "ttv_multi"]
+__all__ = ["AllButOp", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc", "plan_query", "ttv",
+           "ttv_allbut", "ttv_backward", "ttv_multi"]

@@ -135,3 +135,149 @@ def ttv_multi(subs, vals, shape, modes: Sequence[int], vecs, *, flags: int = 0, 
     op = TTVOp(subs, vals, shape, modes, vecs, flags=flags, out_f64=out_f64)
     op.launch()
     return op.result()
+
+
+def _vec_arrays(vecs, order, skip=None):
+    ptrs = (c_void_p * order)()
+    lens = (c_int64 * order)()
+    for j in range(order):
+        v = None if vecs is None else vecs[j]
+        if j == skip or v is None:
+            ptrs[j] = None
+            lens[j] = 0
+        else:
+            _check_tensor(v, f"vecs[{j}]")
+            if not v.is_contiguous():
+                raise ValueError("vectors must be contiguous")
+            ptrs[j] = v.data_ptr()
+            lens[j] = v.numel()
+    return ptrs, lens
+
+
+class AllButOp:
+    """Planned all-but-one product y = X x_{j != keep} v_j (dense, length
+    shape[keep]) with preallocated output and workspace."""
+
+    def __init__(self, subs, vals, shape, keep: int, vecs, *, flags: int = 0, out_f64: bool = False):
+        self.lib = L.load()
+        self.subs, self.vals, self.shape, self.keep = subs, vals, tuple(int(s) for s in shape), int(keep)
+        self.vecs = [None if (j == keep or v is None) else v.contiguous() for j, v in enumerate(vecs)]
+        for j, v in enumerate(self.vecs):
+            if v is not None and v.dtype != vals.dtype:
+                raise TypeError("vectors must have the dtype of vals")
+        self.flags = flags | (L.OUT_F64 if out_f64 else 0)
+        self.desc = coo_desc(subs, vals, self.shape)
+        self.c_vecs, self.c_lens = _vec_arrays(self.vecs, len(self.shape), skip=keep)
+        nb = c_size_t(0)
+        L.check(self.lib.ttv_coo_allbut_workspace(byref(self.desc), self.keep, self.flags, byref(nb)),
+                "ttv_coo_allbut_workspace")
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=subs.device)
+        self.y = torch.empty(self.shape[keep], dtype=_out_value_dtype(vals, out_f64), device=subs.device)
+
+    def launch(self):
+        rc = self.lib.ttv_coo_allbut(byref(self.desc), self.keep, self.c_vecs, self.c_lens, self.y.data_ptr(),
+                                     self.ws.data_ptr(), self.ws.numel(), self.flags, _stream(self.subs.device))
+        L.check(rc, "ttv_coo_allbut")
+
+    def device_error(self) -> int:
+        return self.lib.ttv_check_device_error(self.ws.data_ptr(), _stream(self.subs.device))
+
+
+def ttv_allbut(subs, vals, shape, keep: int, vecs, *, flags: int = 0, out_f64: bool = False):
+    """Product with a vector in every mode except ``keep`` (n_v = d - 1,
+    Sec. 3.3): a dense vector of length shape[keep].  ``vecs`` has one entry
+    per mode; entry ``keep`` is ignored."""
+    op = AllButOp(subs, vals, shape, keep, vecs, flags=flags, out_f64=out_f64)
+    op.launch()
+    return op.y
+
+
+def ttv_backward(subs, vals, shape, kind: str, mode: int, vecs, grad_out, *, want_vecs=None,
+                 want_vals: bool = True, flags: int = 0):
+    """Adjoint of ``ttv`` (kind="sparse": grad_out has one value per output
+    row of ttv in ``mode``) or of ``ttv_allbut`` (kind="allbut": grad_out is
+    dense over the kept mode ``mode``).  Returns (grad_vecs, grad_vals): a list
+    with a gradient per requested mode (None elsewhere) and the gradient with
+    respect to vals (or None)."""
+    lib = L.load()
+    shape = tuple(int(s) for s in shape)
+    d = len(shape)
+    k = L.BWD_SPARSE if kind == "sparse" else L.BWD_ALLBUT
+    if kind not in ("sparse", "allbut"):
+        raise ValueError("kind must be 'sparse' or 'allbut'")
+    desc = coo_desc(subs, vals, shape)
+    if kind == "sparse":
+        want = [mode] if want_vecs is None else list(want_vecs)
+        vv = [None] * d
+        vv[mode] = vecs[mode] if isinstance(vecs, (list, tuple)) else vecs
+        c_vecs, c_lens = _vec_arrays(vv, d)
+    else:
+        want = [j for j in range(d) if j != mode] if want_vecs is None else list(want_vecs)
+        c_vecs, c_lens = _vec_arrays(vecs, d, skip=mode)
+    grad_out = grad_out.contiguous()
+    if grad_out.dtype != vals.dtype:
+        raise TypeError("grad_out must have the dtype of vals")
+    dev = subs.device
+    gv = [None] * d
+    gptrs = (c_void_p * d)()
+    for j in range(d):
+        if j in want:
+            gv[j] = torch.empty(shape[j], dtype=vals.dtype, device=dev)
+            gptrs[j] = gv[j].data_ptr()
+        else:
+            gptrs[j] = None
+    gvals = torch.empty(max(1, vals.numel()), dtype=vals.dtype, device=dev) if want_vals else None
+    nb = c_size_t(0)
+    L.check(lib.ttv_coo_backward_workspace(byref(desc), k, mode, flags, byref(nb)), "ttv_coo_backward_workspace")
+    ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=dev)
+    rc = lib.ttv_coo_backward(byref(desc), k, mode, c_vecs, c_lens, grad_out.data_ptr() if grad_out.numel() else None,
+                              gptrs, gvals.data_ptr() if gvals is not None else None, ws.data_ptr(), ws.numel(),
+                              flags, _stream(dev))
+    L.check(rc, "ttv_coo_backward")
+    L.check(lib.ttv_check_device_error(ws.data_ptr(), _stream(dev)), "device")
+    return gv, (gvals[:vals.numel()] if gvals is not None else None)
+
+
+class TTVAllButFunction(torch.autograd.Function):
+    """y = X x_{j != keep} v_j as an autograd function of the vectors and of
+    vals; the backward runs the library's fused adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, subs, vals, shape, keep, *vecs):
+        ctx.shape, ctx.keep = tuple(shape), int(keep)
+        ctx.save_for_backward(subs, vals, *[v if v is not None else torch.empty(0) for v in vecs])
+        ctx.none = [v is None for v in vecs]
+        return ttv_allbut(subs, vals, shape, keep, list(vecs))
+
+    @staticmethod
+    def backward(ctx, gy):
+        subs, vals, *vs = ctx.saved_tensors
+        vecs = [None if ctx.none[j] else vs[j] for j in range(len(vs))]
+        d = len(ctx.shape)
+        want = [j for j in range(d) if j != ctx.keep and ctx.needs_input_grad[4 + j]]
+        gv, gvals = ttv_backward(subs, vals, ctx.shape, "allbut", ctx.keep, vecs, gy.to(vals.dtype),
+                                 want_vecs=want, want_vals=ctx.needs_input_grad[1])
+        return (None, gvals, None, None, *[gv[j] for j in range(d)])
+
+
+class TTVFunction(torch.autograd.Function):
+    """Sparse TTV in one mode as an autograd function of v and vals; returns
+    the output values (the coordinates are fixed by subs)."""
+
+    @staticmethod
+    def forward(ctx, subs, vals, shape, mode, v):
+        ns, nv, _ = ttv(subs, vals, shape, mode, v)
+        ctx.shape, ctx.mode = tuple(shape), int(mode)
+        ctx.save_for_backward(subs, vals, v)
+        ctx.mark_non_differentiable(ns)
+        return nv, ns
+
+    @staticmethod
+    def backward(ctx, gvals_out, _gs):
+        subs, vals, v = ctx.saved_tensors
+        vecs = [None] * len(ctx.shape)
+        vecs[ctx.mode] = v
+        gv, gvals = ttv_backward(subs, vals, ctx.shape, "sparse", ctx.mode, vecs, gvals_out.to(vals.dtype),
+                                 want_vecs=[ctx.mode] if ctx.needs_input_grad[4] else [],
+                                 want_vals=ctx.needs_input_grad[1])
+        return None, gvals, None, None, gv[ctx.mode]

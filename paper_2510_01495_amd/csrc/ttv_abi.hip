@@ -167,14 +167,9 @@ static int choose_T1(long long total) {
   return (int)std::min<long long>(65536, std::max<long long>(4096, t));
 }
 
-// Plans a single-tensor pipeline run (ncon contracted modes).
-int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, int pipe_mode,
-                PipePlan& P) {
-  int rc = plan_tensor(X, ncon, modes, flags, P.d0, P.form, P.idx64);
-  if (rc) return rc;
+int finish_plan(PipePlan& P) {
   P.count = 1;
-  P.pipe_mode = pipe_mode;
-  P.total = X->nnz;
+  P.total = P.d0.nnz;
   P.d0.base = 0;
   P.levels = levels_of(P.d0);
   P.T1 = choose_T1(P.total);
@@ -182,6 +177,15 @@ int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
   P.tiles1 = (P.total + P.T1 - 1) / P.T1;
   P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1);
   return TTV_OK;
+}
+
+// Plans a single-tensor pipeline run (ncon contracted modes).
+int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, int pipe_mode,
+                PipePlan& P) {
+  int rc = plan_tensor(X, ncon, modes, flags, P.d0, P.form, P.idx64);
+  if (rc) return rc;
+  P.pipe_mode = pipe_mode;
+  return finish_plan(P);
 }
 
 }  // namespace ttv

@@ -1,0 +1,388 @@
+// Dense accumulation kernels: the all-but-one product (n_v = d - 1 vectors,
+// Sec. 3.3) and the adjoints of both products.
+//
+// Each accumulator `a` sums, over the nonzeros e of X,
+//     vals[e] * prod_{j in factor modes, j != key_a} f_j[subs(e, j)]  (* gseg[seg[e]])
+// into a dense vector indexed by subs(e, key_a).  The forward all-but-one
+// product is one accumulator (key = kept mode, factors = the other vectors);
+// the adjoint of the all-but-one product has one accumulator per vector
+// (factors = the vectors with the cotangent in the kept mode); the adjoint of
+// the sparse product keys by the contracted mode with the cotangent gathered
+// through the segment map.  The optional per-nonzero output is the product of
+// all factors (the gradient with respect to vals).
+//
+// Accumulation is atomics-free and deterministic: a block takes tiles of
+// nonzeros in a fixed order, sorts each tile by key in LDS (stable radix
+// sort), reduces every run of equal keys with a segmented scan and adds the
+// run's sum into its private dense LDS partial (one writer per key).  The
+// blocks' partials are summed in a fixed block order in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ttv_dense.h"
+#include "ttv_device.hpp"
+
+namespace ttv {
+
+namespace {
+
+constexpr int NT = kDenseThreads;
+constexpr int NW = NT / 64;
+constexpr int IPT = kDenseIPT;
+constexpr int TA = NT * IPT;  // nonzeros per tile
+constexpr int MAXD = 8;       // LDS digit bits
+
+template <typename IdxT, int F>
+__global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
+  using FO = FormOps<F>;
+  using Acc = typename FO::Acc;
+  using In = typename FO::In;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  // layout: accumulators | keys u32[TA] | idx u16[TA] | pay u64[TA] | cnt u32[NW<<MAXD]
+  Acc* accs = reinterpret_cast<Acc*>(smem);
+  unsigned* sk = reinterpret_cast<unsigned*>(smem + A.acc_bytes);
+  unsigned short* si = reinterpret_cast<unsigned short*>(sk + TA);
+  uint64_t* sp = reinterpret_cast<uint64_t*>(smem + A.acc_bytes + TA * 4 + TA * 2);
+  unsigned* cnt = reinterpret_cast<unsigned*>(sp + TA);
+  __shared__ unsigned wsum[NW];
+  __shared__ Seg<F> wagg[NW];
+  const int tid = threadIdx.x, w = tid >> 6;
+  const unsigned ln = lane_id();
+  for (int i = tid; i < A.acc_total; i += NT) accs[i] = FO::zero();
+  __syncthreads();
+  const gptr<const IdxT> subs = to_global(static_cast<const IdxT*>(A.subs));
+  const gptr<const In> vals = to_global(static_cast<const In*>(A.vals));
+  for (long long t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+    const long long e0 = t * TA;
+    const int n = (int)((A.nnz - e0 < (long long)TA) ? A.nnz - e0 : (long long)TA);
+    // ---- per nonzero: indices of the key modes, products ----
+    unsigned key[kDenseMaxAcc][IPT];
+    uint64_t pay[kDenseMaxAcc][IPT];
+    {
+      uint64_t full[IPT];  // product of all factors (gradient w.r.t. vals)
+      uint64_t pa[kDenseMaxAcc][IPT];
+      In a[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int i = w * 64 * IPT + j * 64 + (int)ln;
+        a[j] = i < n ? vals[e0 + i] : (In)0;
+        full[j] = FO::start_prod((In)1);
+#pragma unroll
+        for (int q = 0; q < kDenseMaxAcc; ++q) {
+          pa[q][j] = FO::start_prod(a[j]);
+          key[q][j] = 0;
+        }
+      }
+      for (int m = 0; m < A.order; ++m) {
+        const bool is_key0 = A.nacc > 0 && A.key_mode[0] == m;
+        const bool is_key1 = A.nacc > 1 && A.key_mode[1] == m;
+        const bool is_key2 = A.nacc > 2 && A.key_mode[2] == m;
+        const bool is_key3 = A.nacc > 3 && A.key_mode[3] == m;
+        const In* fac = static_cast<const In*>(A.fac[m]);
+        if (!fac && !(is_key0 || is_key1 || is_key2 || is_key3)) continue;
+        long long x[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          x[j] = i < n ? (long long)subs[(e0 + i) * A.se + A.sj[m]] : 0;
+          if (A.validate && i < n && (x[j] < 0 || x[j] >= A.dims[m])) {
+            atomicCAS(A.err, 0, TTV_E_INDEX);
+            x[j] = 0;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          if (is_key0) key[0][j] = (unsigned)x[j];
+          if (is_key1) key[1][j] = (unsigned)x[j];
+          if (is_key2) key[2][j] = (unsigned)x[j];
+          if (is_key3) key[3][j] = (unsigned)x[j];
+        }
+        if (fac) {
+          const gptr<const In> f = to_global(fac);
+          In g[IPT];
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) g[j] = f[x[j]];
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            full[j] = FO::mul_prod(full[j], g[j]);
+#pragma unroll
+            for (int q = 0; q < kDenseMaxAcc; ++q)
+              if (q < A.nacc && A.key_mode[q] != m) pa[q][j] = FO::mul_prod(pa[q][j], g[j]);
+          }
+        }
+      }
+      if (A.gseg) {
+        const gptr<const In> gs = to_global(static_cast<const In*>(A.gseg));
+        const gptr<const int32_t> sg = to_global(A.seg);
+        In g[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          g[j] = i < n ? gs[sg[e0 + i]] : (In)0;
+        }
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          full[j] = FO::mul_prod(full[j], g[j]);
+#pragma unroll
+          for (int q = 0; q < kDenseMaxAcc; ++q) pa[q][j] = FO::mul_prod(pa[q][j], g[j]);
+        }
+      }
+      if (A.grad_vals) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          if (i < n) {
+            const double v = FO::to_f64(FO::from_pay(full[j]));
+            if (F == kF64)
+              to_global(static_cast<double*>(A.grad_vals))[e0 + i] = v;
+            else
+              to_global(static_cast<float*>(A.grad_vals))[e0 + i] = (float)v;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kDenseMaxAcc; ++q)
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) pay[q][j] = pa[q][j];
+    }
+    // ---- per accumulator: stable LDS radix sort by key, segmented reduce ----
+#pragma unroll
+    for (int q = 0; q < kDenseMaxAcc; ++q) {
+      if (q >= A.nacc) break;
+      Acc* acc = accs + A.acc_off[q];
+      const int bits = A.key_bits[q];
+      unsigned k[IPT];
+      unsigned ix[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int i = w * 64 * IPT + j * 64 + (int)ln;
+        k[j] = key[q][j];
+        ix[j] = (unsigned)i;
+        if (i < n) sp[i] = pay[q][j];
+      }
+      const int npass = (bits + MAXD - 1) / MAXD;
+      const int dw = npass ? (bits + npass - 1) / npass : 0;
+      const int nb = 1 << dw;
+      const unsigned dmask = (unsigned)nb - 1u;
+      for (int pass = 0; pass < npass; ++pass) {
+        const int sh = pass * dw;
+        for (int c = tid; c < NW * nb; c += NT) cnt[c] = 0u;
+        __syncthreads();
+        unsigned rk[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          rk[j] = 0;
+          // stable rank: same-address lanes of one LDS atomic are served in lane order
+          if (i < n) rk[j] = atomicAdd(&cnt[w * nb + ((k[j] >> sh) & dmask)], 1u);
+        }
+        __syncthreads();
+        {
+          const int E = NW * nb;
+          const int ept = (E + NT - 1) / NT;
+          unsigned v[4], s = 0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int e = tid * ept + c;
+            v[c] = (c < ept && e < E) ? cnt[(e % NW) * nb + e / NW] : 0u;
+            s += v[c];
+          }
+          unsigned tot;
+          unsigned ex = block_excl_scan<NT>(s, wsum, tot);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int e = tid * ept + c;
+            if (c < ept && e < E) cnt[(e % NW) * nb + e / NW] = ex;
+            ex += v[c];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          if (i < n) {
+            const unsigned dest = cnt[w * nb + ((k[j] >> sh) & dmask)] + rk[j];
+            sk[dest] = k[j];
+            si[dest] = (unsigned short)ix[j];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          if (i < n) {
+            k[j] = sk[i];
+            ix[j] = si[i];
+          }
+        }
+        __syncthreads();
+      }
+      // k[], ix[] now hold the sorted order in the same (wave, item, lane)
+      // positions.  Segmented scan in rounds of 64 consecutive positions.
+      uint64_t hm[IPT];
+      Acc val[IPT];
+      // heads need the previous position's key: read the sorted keys back
+      if (npass == 0) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          if (i < n) sk[i] = k[j];
+        }
+        __syncthreads();
+      }
+      {
+        Acc c = FO::zero();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          const bool hd = i < n && (i == 0 || sk[i - 1] != k[j]);
+          hm[j] = ballot(hd);
+          Seg<F> e;
+          e.f = hd ? 1 : 0;
+          e.v = i < n ? FO::from_pay(sp[ix[j]]) : FO::zero();
+          e = wave_seg_scan<F>(e);
+          val[j] = e.f ? e.v : FO::add(c, e.v);
+          c = FO::shfl_last(val[j]);
+        }
+        if (ln == 0) {
+          bool any = false;
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) any = any || hm[j] != 0;
+          wagg[w].f = any ? 1 : 0;
+          wagg[w].v = c;
+        }
+      }
+      __syncthreads();
+      {
+        Seg<F> cw;
+        cw.f = 0;
+        cw.v = FO::zero();
+        for (int r = 0; r < w; ++r) cw = seg_combine<F>(cw, wagg[r]);
+        bool lead = true;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const uint64_t upto = hm[j] & (~0ull >> (63 - ln));
+          if (lead && upto == 0) val[j] = FO::add(cw.v, val[j]);
+          lead = lead && hm[j] == 0;
+        }
+      }
+      // segment ends add their run into the block's dense partial
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int i = w * 64 * IPT + j * 64 + (int)ln;
+        if (i < n) {
+          const bool end = (i == n - 1) || sk[i + 1] != k[j];
+          if (end) acc[k[j]] = FO::add(acc[k[j]], val[j]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // block partials, FP64
+  for (int i = tid; i < A.acc_total; i += NT)
+    to_global(A.partials)[(size_t)blockIdx.x * A.acc_total + i] = FO::to_f64(accs[i]);
+}
+
+// Sum the block partials of every output entry in block order (FP64).
+// Block = 64 entries x 16 groups of blocks; group sums are added in order.
+__global__ __launch_bounds__(1024) void k_dense_combine(DenseArgs A, int nparts) {
+  __shared__ double part[16][64];
+  const int dd = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const long long c0 = (long long)blockIdx.x * 64;
+  const long long c = c0 + dd;
+  const int per = (nparts + 15) / 16;
+  const int b0 = g * per, b1 = std::min(nparts, b0 + per);
+  double s = 0.0;
+  if (c < A.acc_total) {
+    const gptr<const double> P = to_global((const double*)A.partials);
+    for (int b = b0; b < b1; ++b) s += P[(size_t)b * A.acc_total + c];
+  }
+  part[g][dd] = s;
+  __syncthreads();
+  if (g == 0 && c < A.acc_total) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += part[q][dd];
+    // which accumulator / entry
+    int q = 0;
+    while (q + 1 < A.nacc && c >= A.acc_off[q + 1]) ++q;
+    const long long i = c - A.acc_off[q];
+    if (A.out_f64)
+      to_global(static_cast<double*>(A.out[q]))[i] = t;
+    else
+      to_global(static_cast<float*>(A.out[q]))[i] = (float)t;
+  }
+}
+
+// Dense output from a sparse one: zero-fill, then scatter the values.
+__global__ __launch_bounds__(256) void k_fill_zero(void* out, long long n_out, int f64) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_out;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (f64)
+      static_cast<double*>(out)[i] = 0.0;
+    else
+      static_cast<float*>(out)[i] = 0.f;
+  }
+}
+
+// vals: FP64 values of the sparse result, idx: its single index column
+template <typename IdxT>
+__global__ __launch_bounds__(256) void k_scatter_dense(const IdxT* idx, const double* vals, const long long* cnt,
+                                                       void* out, long long n_out, int f64) {
+  const long long m = *cnt;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long k = (long long)idx[i];
+    if (k < 0 || k >= n_out) continue;
+    if (f64)
+      static_cast<double*>(out)[k] = vals[i];
+    else
+      static_cast<float*>(out)[k] = (float)vals[i];
+  }
+}
+
+template <typename IdxT, int F>
+int launch_dense_impl(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
+  hipFuncSetAttribute((const void*)k_dense<IdxT, F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_dense<IdxT, F>), dim3(grid), dim3(kDenseThreads), lds, s, A);
+  const int cb = (int)((A.acc_total + 63) / 64);
+  hipLaunchKernelGGL(k_dense_combine, dim3(std::max(cb, 1)), dim3(1024), 0, s, A, grid);
+  return 0;
+}
+
+}  // namespace
+
+size_t dense_tile_lds() { return (size_t)TA * (4 + 2 + 8) + (size_t)(NW << MAXD) * 4; }
+
+int launch_dense(const DenseArgs& A, int idx64, int form, int grid, size_t lds, hipStream_t s) {
+  if (form == kF64) {
+    if (idx64) return launch_dense_impl<long long, kF64>(A, grid, lds, s);
+    return launch_dense_impl<int, kF64>(A, grid, lds, s);
+  }
+  if (idx64) return launch_dense_impl<long long, kC32>(A, grid, lds, s);
+  return launch_dense_impl<int, kC32>(A, grid, lds, s);
+}
+
+int launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 4);
+  const int g = (int)std::min<long long>(std::max<long long>(1, (n + 255) / 256), 1024);
+  hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, p, n, 0);
+  return 0;
+}
+
+int launch_densify(const void* idx, int idx64, const void* vals, const long long* cnt, void* out, long long n_out,
+                   int f64, int cus, hipStream_t s) {
+  const int g = (int)std::min<long long>(std::max<long long>(1, (n_out + 255) / 256), 4LL * cus);
+  hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, out, n_out, f64);
+  if (idx64)
+    hipLaunchKernelGGL(k_scatter_dense<long long>, dim3(g), dim3(256), 0, s, (const long long*)idx,
+                       (const double*)vals, cnt, out, n_out, f64);
+  else
+    hipLaunchKernelGGL(k_scatter_dense<int>, dim3(g), dim3(256), 0, s, (const int*)idx, (const double*)vals, cnt,
+                       out, n_out, f64);
+  return 0;
+}
+
+}  // namespace ttv

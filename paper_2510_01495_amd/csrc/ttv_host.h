@@ -28,21 +28,15 @@ struct PipePlan {
   Layout L{};
 };
 
-// Dense (all-but-one / adjoint) accumulation plan.
-struct DensePlan {
-  TDesc D{};
-  int keep = 0;
-  int form = kF64;
-  int idx64 = 1;
-  int nkeep = 0;
-  int tile = 4096;
-  int blocks = 256;
-  int cus = 256;
-  size_t ws_bytes = 0;
-};
-
 void set_last_hip_error(int e);
 int device_cus();
 int launch_pipeline(const PipePlan& P, void* ws, hipStream_t s);
+int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, TDesc& D, int& form, int& idx64);
+int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, int pipe_mode, PipePlan& P);
+Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1);
+int finish_plan(PipePlan& P);  // levels, tiles and layout of a planned single tensor
+int launch_zero(void* p, size_t bytes, hipStream_t s);
+
+constexpr int kAssumedCUs = 256;  // MI355X; tiling never depends on the device queried at call time
 
 }  // namespace ttv

@@ -58,6 +58,8 @@ struct TDesc {
   void* out_vals;               // nnz_out values
   long long* out_nnz;           // device scalar
   int32_t* seg_out;             // segment map (kPipeSegMap)
+  const void* segfac;           // optional factor of every payload, gathered through segidx
+  const int32_t* segidx;
   long long nnz;
   long long base;               // first record of this tensor in the record buffers
   long long stride_e, stride_j; // subs element (e, j) at subs[e*stride_e + j*stride_j]

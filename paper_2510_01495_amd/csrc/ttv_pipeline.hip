@@ -113,11 +113,15 @@ struct RawSrc {
   const In* vec[kMaxOrder];
   long long sj[kMaxOrder];
   long long dim[kMaxOrder];
-  int shift[kMaxOrder];  // key shift of a remaining mode, -1 if contracted
+  int shift[kMaxOrder];  // key shift of a remaining mode, -1 otherwise
   int width[kMaxOrder];
+  const In* segfac;
+  const int32_t* segidx;
   __device__ __forceinline__ void set(const TDesc& D) {
     subs = static_cast<const IdxT*>(D.subs);
     vals = static_cast<const In*>(D.vals);
+    segfac = static_cast<const In*>(D.segfac);
+    segidx = D.segidx;
     se = D.stride_e;
     order = D.order;
     validate = D.validate;
@@ -157,7 +161,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e
   const bool validate = S.validate != 0;
   for (int m = 0; m < order; ++m) {
     const int sh = S.shift[m];
-    if (PM == kPipeSegMap && sh < 0) continue;
+    if (sh < 0 && (PM == kPipeSegMap || !S.vec[m])) continue;
     const long long sj = S.sj[m];
     long long x[IPT];
 #pragma unroll
@@ -178,7 +182,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e
       const int wd = S.width[m];
 #pragma unroll
       for (int j = 0; j < IPT; ++j) key[j] |= (uint64_t)field(x[j], wd) << sh;
-    } else {
+    } else if (S.vec[m]) {
       const gptr<const In> vec = to_global(S.vec[m]);
       In g[IPT];
 #pragma unroll
@@ -186,6 +190,15 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e
 #pragma unroll
       for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[j]);
     }
+  }
+  if (PM != kPipeSegMap && S.segfac) {
+    const gptr<const In> sf = to_global(S.segfac);
+    const gptr<const int32_t> sx = to_global(S.segidx);
+    In g[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) g[j] = ((long long)j * 64 < n_left) ? sf[sx[e0 + (long long)j * 64]] : (In)0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[j]);
   }
 }
 
