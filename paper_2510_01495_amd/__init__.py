@@ -9,6 +9,7 @@ only supplies device memory and streams.
 from . import _lib  # noqa: F401
 from .api import (  # noqa: F401
     AllButOp,
+    BatchedTTV,
     TTVAllButFunction,
     TTVFunction,
     TTVOp,
@@ -20,5 +21,5 @@ from .api import (  # noqa: F401
     ttv_multi,
 )
 
-__all__ = ["AllButOp", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc", "plan_query", "ttv",
+__all__ = ["AllButOp", "BatchedTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc", "plan_query", "ttv",
            "ttv_allbut", "ttv_backward", "ttv_multi"]

@@ -281,3 +281,86 @@ class TTVFunction(torch.autograd.Function):
                                  want_vecs=[ctx.mode] if ctx.needs_input_grad[4] else [],
                                  want_vals=ctx.needs_input_grad[1])
         return None, gvals, None, None, gv[ctx.mode]
+
+
+class BatchedTTV:
+    """Sparse TTV of many independent tensors (each with its own mode and
+    vector) in one fixed sequence of persistent kernels.  ``members`` is a
+    list of (subs, vals, shape, mode, v).  Outputs are preallocated (capacity
+    nnz of each tensor); ``launch()`` is capture-safe, so ``graph()`` can
+    record it into a hipGraph (torch.cuda.CUDAGraph) for replay."""
+
+    def __init__(self, members, *, tune_cache: Optional[str] = None, flags: int = 0, out_f64: bool = False):
+        self.lib = L.load()
+        self.members = members
+        n = len(members)
+        if n < 1:
+            raise ValueError("empty batch")
+        dev = members[0][0].device
+        self.device = dev
+        self.flags = flags | (L.OUT_F64 if out_f64 else 0)
+        self.descs = (L.CooDesc * n)()
+        self.c_modes = (c_int32 * n)()
+        self.c_vs = (c_void_p * n)()
+        self.c_os = (c_void_p * n)()
+        self.c_ov = (c_void_p * n)()
+        self.out_subs, self.out_vals, self.newshape = [], [], []
+        self.keep = []  # keep every tensor the library reads alive
+        for i, (subs, vals, shape, mode, v) in enumerate(members):
+            shape = tuple(int(s) for s in shape)
+            v = v.contiguous()
+            self.keep.append((subs, vals, v))
+            self.descs[i] = coo_desc(subs, vals, shape)
+            self.c_modes[i] = int(mode)
+            self.c_vs[i] = v.data_ptr()
+            nnz, d = subs.shape[0], len(shape)
+            os_ = torch.empty((max(nnz, 1), d - 1), dtype=subs.dtype, device=dev)
+            ov = torch.empty(max(nnz, 1), dtype=_out_value_dtype(vals, out_f64), device=dev)
+            self.out_subs.append(os_)
+            self.out_vals.append(ov)
+            self.c_os[i] = os_.data_ptr()
+            self.c_ov[i] = ov.data_ptr()
+            self.newshape.append(tuple(s for j, s in enumerate(shape) if j != mode))
+        self.out_nnz = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.plan = c_void_p()
+        cache = tune_cache.encode() if tune_cache else None
+        L.check(self.lib.ttv_batch_plan_create(n, self.descs, self.c_modes, self.c_vs, self.c_os, self.c_ov,
+                                               self.out_nnz.data_ptr(), self.flags, cache, byref(self.plan)),
+                "ttv_batch_plan_create")
+        nb = c_size_t(0)
+        L.check(self.lib.ttv_batch_workspace(self.plan, byref(nb)), "ttv_batch_workspace")
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=dev)
+
+    def launch(self):
+        L.check(self.lib.ttv_coo_batched(self.plan, self.ws.data_ptr(), self.ws.numel(), _stream(self.device)),
+                "ttv_coo_batched")
+
+    def autotune(self):
+        L.check(self.lib.ttv_batch_autotune(self.plan, self.ws.data_ptr(), self.ws.numel(), _stream(self.device)),
+                "ttv_batch_autotune")
+
+    def graph(self):
+        """Capture one ``launch()`` into a CUDAGraph (hipGraph) and return it."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.launch()  # warm-up outside the capture
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.graph(g, stream=s):
+            self.launch()
+        return g
+
+    def results(self):
+        L.check(self.lib.ttv_check_device_error(self.ws.data_ptr(), _stream(self.device)), "device")
+        counts = self.out_nnz.cpu().tolist()
+        return [(self.out_subs[i][:m], self.out_vals[i][:m], self.newshape[i]) for i, m in enumerate(counts)]
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None) is not None and self.plan.value:
+                self.lib.ttv_batch_plan_destroy(self.plan)
+                self.plan = c_void_p()
+        except Exception:
+            pass

@@ -1194,7 +1194,8 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     const int gt = l == 1 ? (int)std::max<long long>(1, std::min<long long>(P.tiles1, 8LL * cus)) : 4 * cus;
     const int gj = l == 1 ? std::max(1, P.count) : 2 * cus;
     hipLaunchKernelGGL(k_hist<IdxT>, dim3(gt), dim3(256), 0, s, W, l, T);
-    hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::max(1, P.count * 64) : 4 * cus), dim3(1024), 0, s, W, l);
+    hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 4 * cus), dim3(1024),
+                       0, s, W, l);
     hipLaunchKernelGGL(k_classify, dim3(std::min(gj, 4 * cus)), dim3(1024), 0, s, W, l, Tn, P.levels);
     hipLaunchKernelGGL((k_scatter<IdxT, F, PM>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
   }

@@ -1,0 +1,111 @@
+"""CPU tests of the C ABI: the library loads, exports every symbol the
+header declares, and validates arguments / plans key layouts without a GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2510_01495_amd import _lib as L
+    return L, L.load()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ttv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ttv_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L, lib = _lib()
+    names = _declared()
+    assert "ttv_coo" in names and "ttv_coo_batched" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} is declared in include/ttv.h but not exported"
+    assert set(names) <= set(L.SIGNATURES), "binding lacks a signature"
+
+
+def _desc(shape, nnz, idx=1, val=1, subs=1, vals=1):
+    L, _ = _lib()
+    d = L.CooDesc()
+    d.order = len(shape)
+    d.index_dtype = idx
+    d.value_dtype = val
+    d.nnz = nnz
+    for j, s in enumerate(shape):
+        d.shape[j] = s
+    d.subs = subs  # never dereferenced by the host-only calls
+    d.stride_e = len(shape)
+    d.stride_j = 1
+    d.vals = vals
+    return d
+
+
+def _query(d, modes, flags=0):
+    L, lib = _lib()
+    info = L.PlanInfo()
+    m = (ctypes.c_int32 * len(modes))(*modes)
+    rc = lib.ttv_plan_query(ctypes.byref(d), len(modes), m, flags, ctypes.byref(info))
+    return rc, info
+
+
+def test_plan_key_layout():
+    rc, info = _query(_desc((100, 80, 60), 10_000), [2])
+    assert rc == 0
+    assert info.nrem == 2 and list(info.rem_modes[:2]) == [0, 1]
+    assert list(info.bits[:2]) == [7, 7] and info.key_bits == 14
+    assert list(info.shift[:2]) == [7, 0]  # first remaining mode most significant
+    rc, info = _query(_desc((10_000,) * 3, 10_000_000), [0])
+    assert rc == 0 and info.key_bits == 28 and info.digit1_bits == 12
+    rc, info = _query(_desc((2000,) * 4, 50_000_000), [1])
+    assert rc == 0 and info.key_bits == 33 and info.levels >= 3
+    rc, info = _query(_desc((1, 50, 1), 100), [1])
+    assert rc == 0 and info.key_bits == 0 and info.levels == 1
+    assert info.workspace_bytes > 0
+
+
+def test_error_codes():
+    L, lib = _lib()
+    E = dict(NULL=-1, ORDER=-2, MODE=-3, SHAPE=-4, DTYPE=-5, KEYBITS=-6, WORKSPACE=-7, SIZE=-10)
+    assert _query(_desc((5,), 3), [0])[0] == E["ORDER"]
+    d9 = _desc((5,) * 8, 3)
+    d9.order = 9
+    assert _query(d9, [0])[0] == E["ORDER"]
+    assert _query(_desc((5, 6, 7), 3), [3])[0] == E["MODE"]
+    assert _query(_desc((5, 6, 7), 3), [1, 1])[0] == E["MODE"]
+    assert _query(_desc((5, 6, 7), 3), [0, 1, 2])[0] == E["MODE"]
+    assert _query(_desc((5, 0, 7), 3), [0])[0] == E["SHAPE"]
+    assert _query(_desc((5, 6, 7), 3, idx=7), [0])[0] == E["DTYPE"]
+    assert _query(_desc((5, 6, 7), 3, val=9), [0])[0] == E["DTYPE"]
+    assert _query(_desc((5, 6, 7), 3, subs=None), [0])[0] == E["NULL"]
+    assert _query(_desc((2 ** 40,) * 3, 3), [0])[0] == E["KEYBITS"]
+    assert _query(_desc((5, 6, 7), 2 ** 31), [0])[0] == E["SIZE"]
+    assert _query(_desc((5, 6, 7), 0, subs=None, vals=None), [0])[0] == 0  # empty tensor is fine
+    d = _desc((5, 6, 7), 3)
+    v = ctypes.c_void_p(1)
+    nnz = ctypes.c_void_p(1)
+    # too small a workspace is rejected before anything is enqueued
+    rc = lib.ttv_coo(ctypes.byref(d), 1, v, 6, v, v, nnz, v, 16, 0, None)
+    assert rc == E["WORKSPACE"]
+    rc = lib.ttv_coo(ctypes.byref(d), 1, v, 5, v, v, nnz, v, 1 << 40, 0, None)
+    assert rc == E["SHAPE"]
+    assert lib.ttv_strerror(E["KEYBITS"]).decode().startswith("remaining-mode")
+    assert lib.ttv_version() >= 100
+
+
+def test_workspace_queries():
+    L, lib = _lib()
+    d = _desc((10_000,) * 3, 10_000_000)
+    nb = ctypes.c_size_t(0)
+    assert lib.ttv_coo_workspace(ctypes.byref(d), 0, 0, ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 16 * 10_000_000  # two record buffers at least
+    assert lib.ttv_coo_allbut_workspace(ctypes.byref(d), 0, 0, ctypes.byref(nb)) == 0 and nb.value > 0
+    for kind in (0, 1):
+        assert lib.ttv_coo_backward_workspace(ctypes.byref(d), kind, 0, 0, ctypes.byref(nb)) == 0
+    assert lib.ttv_coo_backward_workspace(ctypes.byref(d), 5, 0, 0, ctypes.byref(nb)) == -12
