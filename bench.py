@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Sparse TTV benchmark on one MI355X; prints one JSON line.
+
+Workload (all synthetic, seeded): a 10^4 x 10^4 x 10^4 COO tensor with 1e7
+distinct uniformly drawn coordinates, int64 indices, FP64 values U[0,1), and
+one U[0,1) FP64 vector per mode.  One step is the whole hot path on it:
+ttv_coo in mode 0, 1 and 2 (sparse results, sorted and deduplicated) and the
+all-but-one product keeping mode 0 (dense result).  ``value`` counts the
+nonzeros every product in the step consumed per second (4 x 1e7 per step),
+with inputs resident in HBM and outputs preallocated.
+
+Beside it:
+  roofline      the dominant kernel (the leaf sort-reduce-write kernel of
+                ttv_coo), its algorithmic bytes per launch over its average
+                duration measured with HIP events inside the timed region;
+                traffic is the rocprofv3 FETCH_SIZE + WRITE_SIZE of that
+                kernel (from profiles/, if taken on the current source).
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample (the first
+                nonzeros of the same tensor, one mode), single thread.
+  batched       512 uneven FP32 tensors in one batched launch (compensated
+                sums) against one plain FP64 ttv_coo call per tensor, with
+                the largest relative error of sampled members.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def kernel_traffic(name, workload):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            t = json.load(f)
+        src = os.path.join(ROOT, "paper_2510_01495_amd", "csrc", t["source"])
+        if sha(src) != t["source_sha"]:
+            return None
+        return float(t["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(X, mode, v, budget_s):
+    import numpy as np
+    import oracle
+    n = 50_000
+    t0 = time.perf_counter()
+    oracle.ttv(X.subs[:n], X.vals[:n], X.shape, mode, v)
+    rate = n / (time.perf_counter() - t0)
+    n = int(min(X.nnz, max(n, rate * budget_s)))
+    t0 = time.perf_counter()
+    oracle.ttv(X.subs[:n], X.vals[:n], X.shape, mode, v)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} nonzeros of the 1e7-nnz tensor, ttv in mode {mode} "
+                      f"(FP64 oracle: lexsort + fsum per output), {dt:.1f} s"}
+
+
+def sampled_error(X, mode, v, gs, gv, nsample=300, seed=0):
+    """Largest relative error over sampled output rows (oracle per row)."""
+    import numpy as np
+    import oracle
+    m = gs.shape[0]
+    rng = np.random.default_rng(seed)
+    rows = np.unique(rng.integers(0, m, size=min(nsample, m)))
+    coords = gs[rows].cpu().numpy()
+    want = oracle.ttv_entries(X.subs, X.vals, X.shape, mode, v, coords)
+    got = gv[rows].cpu().numpy().astype(np.float64)
+    return float(np.max(np.abs(got - want) / np.abs(want)))
+
+
+def batched_comparison(steps):
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2510_01495_amd as P
+    import synth
+    t0 = time.perf_counter()
+    ms = synth.workload_batch(count=512)
+    log(f"batch generated in {time.perf_counter() - t0:.1f}s, nnz {sum(m.X.nnz for m in ms)}")
+    dev = torch.device("cuda:0")
+    members32, ops64 = [], []
+    for m in ms:
+        subs = torch.from_numpy(m.X.subs).to(dev)
+        vals = torch.from_numpy(m.X.vals).to(dev)
+        v = torch.from_numpy(m.v).to(dev)
+        members32.append((subs, vals, m.X.shape, m.mode, v))
+        ops64.append(P.TTVOp(subs.long(), vals.double(), m.X.shape, [m.mode], [v.double()]))
+    B = P.BatchedTTV(members32)
+    B.autotune()
+    g = B.graph()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1) / steps
+    for op in ops64:
+        op.launch()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(max(1, steps // 4)):
+        for op in ops64:
+            op.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    t_64 = e0.elapsed_time(e1) / max(1, steps // 4)
+    # accuracy of the batched FP32 form on sampled members (oracle per row)
+    res = B.results()
+    worst = 0.0
+    picks = sorted(range(len(ms)), key=lambda i: ms[i].X.nnz)[::32]
+    for i in picks:
+        m = ms[i]
+        worst = max(worst, sampled_error(m.X, m.mode, m.v, res[i][0], res[i][1], nsample=100, seed=i))
+    return {"tensors": len(ms), "nnz": int(sum(m.X.nnz for m in ms)), "fp32_batched_graph_ms": round(t_b, 3),
+            "fp64_per_tensor_ms": round(t_64, 3), "speedup": round(t_64 / t_b, 2),
+            "max_rel_err_sampled": worst, "tuning": "autotuned T1/r1"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 1e7 nonzeros (tests only)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2510_01495_amd as P
+    from paper_2510_01495_amd import _lib as L
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    X, vecs = synth.workload_uniform(scale=args.scale)
+    log(f"generated {X.nnz} nonzeros in {time.perf_counter() - t0:.1f}s")
+    subs = torch.from_numpy(X.subs).to(dev)
+    vals = torch.from_numpy(X.vals).to(dev)
+    gv = [torch.from_numpy(w).to(dev) for w in vecs]
+    t0 = time.perf_counter()
+    ops = [P.TTVOp(subs, vals, X.shape, [m], [gv[m]]) for m in range(3)]
+    ab = P.AllButOp(subs, vals, X.shape, 0, [None, gv[1], gv[2]])
+    ops[0].launch()
+    torch.cuda.synchronize()
+    first_call_ms = (time.perf_counter() - t0) * 1e3
+
+    def step():
+        for op in ops:
+            op.launch()
+        ab.launch()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # HIP events around every launch of the dominant kernel, on its stream
+    K = args.steps
+    nprof = 3 * K
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(nprof)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(nprof)]
+    for e in ev_s + ev_e:  # torch creates the HIP event on first record
+        e.record()
+    torch.cuda.synchronize()
+    from ctypes import c_void_p
+    cs = (c_void_p * nprof)(*[e.cuda_event for e in ev_s])
+    ce = (c_void_p * nprof)(*[e.cuda_event for e in ev_e])
+    lib = L.load()
+    L.check(lib.ttv_profile_events(L.PROF_FINISH, cs, ce, nprof), "ttv_profile_events")
+
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    s0.record()
+    for _ in range(K):
+        step()
+    s1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    nrec = lib.ttv_profile_count()
+    lib.ttv_profile_events(L.PROF_NONE, None, None, 0)
+    ms_step = s0.elapsed_time(s1) / K
+    fin_ms = sum(ev_s[i].elapsed_time(ev_e[i]) for i in range(min(nrec, nprof))) / max(1, min(nrec, nprof))
+
+    nnz = X.nnz
+    nnz_out = [int(op.out_nnz.item()) for op in ops]
+    value = 4 * nnz / (ms_step * 1e-3)
+    # algorithmic bytes of one finish launch: read every 16-byte record once,
+    # write every output row once ((d-1) int64 indices + one FP64 value)
+    fin_bytes = 16 * nnz + np.mean(nnz_out) * (2 * 8 + 8)
+    achieved = fin_bytes / (fin_ms * 1e-3) / 1e9
+    traffic = kernel_traffic("finish", "uniform1e7")
+
+    # correctness of what was timed: sampled rows against the oracle
+    err = max(sampled_error(X, m, vecs[m], ops[m].out_subs[:nnz_out[m]], ops[m].out_vals[:nnz_out[m]], 100, m)
+              for m in range(3))
+    for op in ops:
+        L.check(op.device_error(), "device")
+    # effective bandwidth of the step: algorithmic bytes of all four products
+    b_ttv = [nnz * (3 * 8 + 8) + X.shape[m] * 8 + nnz_out[m] * (2 * 8 + 8) for m in range(3)]
+    b_ab = nnz * (3 * 8 + 8) + 2 * 10_000 * 8 + 10_000 * 8
+    eff = (sum(b_ttv) + b_ab) / (ms_step * 1e-3) / 1e9
+
+    out = {
+        "metric": "sparse TTV nnz/s + % HBM peak; batched FP32 vs plain FP64 at stated err",
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "10^4 x 10^4 x 10^4 COO, 1e7 distinct uniform coordinates, int64 indices, "
+                               "FP64 U[0,1) values; ttv in modes 0, 1, 2 + all-but-one keeping mode 0",
+                   "nnz": nnz, "nnz_out": nnz_out, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_finish (leaf sort + segmented reduce + write)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_us": fin_ms * 1e3, "alg_bytes_per_launch": fin_bytes},
+        "step_effective_GBps": eff,
+        "per_step_wall_ms": wall * 1e3 / K,
+        "first_call_ms": first_call_ms,
+        "max_rel_err_sampled": err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(X, 0, vecs[0], args.cpu_budget)
+    if not args.no_batch:
+        out["batched"] = batched_comparison(max(3, K // 2))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

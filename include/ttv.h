@@ -230,6 +230,20 @@ int ttv_coo_batched(const ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_s
 void ttv_batch_plan_destroy(ttv_batch_plan* plan);
 
 /*
+ * Measurement hook.  While set, the library records the caller's HIP events
+ * starts[k] / stops[k] on the launch stream around the k-th launch of one of
+ * its kernels (k counts up to `capacity`, further launches are not
+ * recorded), so a benchmark can time that kernel inside its timed region.
+ * kernel: TTV_PROF_NONE disables; TTV_PROF_FINISH the leaf sort-reduce-write
+ * kernel; TTV_PROF_SCATTER1 the first-level bucket scatter; TTV_PROF_HIST1
+ * its histogram; TTV_PROF_DENSE the dense accumulation kernel.  Not
+ * thread-safe; for measurement only.  ttv_profile_count returns k.
+ */
+enum { TTV_PROF_NONE = 0, TTV_PROF_FINISH = 1, TTV_PROF_SCATTER1 = 2, TTV_PROF_HIST1 = 3, TTV_PROF_DENSE = 4 };
+int ttv_profile_events(int32_t kernel, void* const* starts, void* const* stops, int32_t capacity);
+int ttv_profile_count(void);
+
+/*
  * Synchronises `stream` and returns the first device-side error recorded in
  * workspace `ws` by the last call that used it (TTV_OK if none), e.g.
  * TTV_E_INDEX for an out-of-range index under TTV_VALIDATE.

@@ -17,6 +17,7 @@ I32, I64 = 0, 1
 F32, F64 = 0, 1
 VALIDATE, OUT_F64 = 0x1, 0x2
 BWD_SPARSE, BWD_ALLBUT = 0, 1
+PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE = 0, 1, 2, 3, 4
 
 
 class CooDesc(ctypes.Structure):
@@ -64,6 +65,8 @@ SIGNATURES = {
     "ttv_coo_batched": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "ttv_batch_plan_destroy": (None, [c_void_p]),
     "ttv_check_device_error": (c_int32, [c_void_p, c_void_p]),
+    "ttv_profile_events": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p), c_int32]),
+    "ttv_profile_count": (c_int32, []),
 }
 
 _lib = None
@@ -73,6 +76,11 @@ class TTVError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
         msg = strerror(status)
+        if status == -9:  # TTV_E_HIP: name the runtime error
+            try:
+                msg += f" (hipError {load().ttv_last_hip_error()})"
+            except Exception:
+                pass
         super().__init__(f"{where}: {msg} (status {status})" if where else f"{msg} (status {status})")
 
 

@@ -16,6 +16,23 @@ namespace ttv {
 static thread_local int g_last_hip_error = 0;
 void set_last_hip_error(int e) { g_last_hip_error = e; }
 
+struct ProfHook {
+  int kernel = 0;
+  int count = 0;
+  std::vector<void*> starts, stops;
+};
+static ProfHook g_prof;
+
+void prof_begin(int kernel, hipStream_t s) {
+  if (g_prof.kernel != kernel || g_prof.count >= (int)g_prof.starts.size()) return;
+  hipEventRecord(static_cast<hipEvent_t>(g_prof.starts[g_prof.count]), s);
+}
+void prof_end(int kernel, hipStream_t s) {
+  if (g_prof.kernel != kernel || g_prof.count >= (int)g_prof.stops.size()) return;
+  hipEventRecord(static_cast<hipEvent_t>(g_prof.stops[g_prof.count]), s);
+  ++g_prof.count;
+}
+
 int device_cus() {
   static std::mutex mu;
   static int cache[64] = {0};
@@ -280,6 +297,17 @@ int ttv_coo(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len, v
   const int64_t lens[1] = {v_len};
   return ttv_coo_multi(X, 1, &mode, vecs, lens, out_subs, out_vals, out_nnz, ws, ws_bytes, flags, stream);
 }
+
+int ttv_profile_events(int32_t kernel, void* const* starts, void* const* stops, int32_t capacity) {
+  if (kernel != TTV_PROF_NONE && (!starts || !stops || capacity < 0)) return TTV_E_NULL;
+  g_prof.kernel = kernel;
+  g_prof.starts.assign(starts, starts + (kernel ? capacity : 0));
+  g_prof.stops.assign(stops, stops + (kernel ? capacity : 0));
+  g_prof.count = 0;
+  return TTV_OK;
+}
+
+int ttv_profile_count(void) { return g_prof.count; }
 
 int ttv_check_device_error(const void* ws, ttv_stream_t stream) {
   if (!ws) return TTV_E_NULL;

@@ -258,6 +258,7 @@ int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
   if (!ws || ws_bytes < W.total) return TTV_E_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
+  (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   const int out_f64 = (form == kF64 || (flags & TTV_OUT_F64)) ? 1 : 0;
   const void* fac[TTV_MAX_ORDER] = {nullptr};
   for (int j = 0; j < X->order; ++j) fac[j] = (j == keep) ? nullptr : vecs[j];
@@ -315,6 +316,7 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, 
   if (!grad_out && X->nnz > 0) return TTV_E_NULL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
+  (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   const int out_f64 = form == kF64 ? 1 : 0;  // gradients have the value type of X
   Pass passes[TTV_MAX_ORDER];
   int npass, fb[TTV_MAX_ORDER], nfb;

@@ -22,6 +22,7 @@
 
 #include "ttv_dense.h"
 #include "ttv_device.hpp"
+#include "ttv_host.h"
 
 namespace ttv {
 
@@ -346,7 +347,9 @@ __global__ __launch_bounds__(256) void k_scatter_dense(const IdxT* idx, const do
 template <typename IdxT, int F>
 int launch_dense_impl(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
   hipFuncSetAttribute((const void*)k_dense<IdxT, F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  prof_begin(TTV_PROF_DENSE, s);
   hipLaunchKernelGGL((k_dense<IdxT, F>), dim3(grid), dim3(kDenseThreads), lds, s, A);
+  prof_end(TTV_PROF_DENSE, s);
   const int cb = (int)((A.acc_total + 63) / 64);
   hipLaunchKernelGGL(k_dense_combine, dim3(std::max(cb, 1)), dim3(1024), 0, s, A, grid);
   return 0;

@@ -37,6 +37,10 @@ Layout make_layout(long long total, int count, int levels, int T1, int T2, long 
 int finish_plan(PipePlan& P);  // levels, tiles and layout of a planned single tensor
 int launch_zero(void* p, size_t bytes, hipStream_t s);
 
+// measurement hook (see ttv_profile_events)
+void prof_begin(int kernel, hipStream_t s);
+void prof_end(int kernel, hipStream_t s);
+
 constexpr int kAssumedCUs = 256;  // MI355X; tiling never depends on the device queried at call time
 
 }  // namespace ttv

@@ -1182,6 +1182,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
 // ---------------------------------------------------------------------------
 template <typename IdxT, int F, int PM>
 static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
+  (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   WsView W;
   W.b = static_cast<char*>(ws);
   W.L = P.L;
@@ -1193,17 +1194,23 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     const int Tn = P.T2;
     const int gt = l == 1 ? (int)std::max<long long>(1, std::min<long long>(P.tiles1, 8LL * cus)) : 4 * cus;
     const int gj = l == 1 ? std::max(1, P.count) : 2 * cus;
+    if (l == 1) prof_begin(TTV_PROF_HIST1, s);
     hipLaunchKernelGGL(k_hist<IdxT>, dim3(gt), dim3(256), 0, s, W, l, T);
+    if (l == 1) prof_end(TTV_PROF_HIST1, s);
     hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 4 * cus), dim3(1024),
                        0, s, W, l);
     hipLaunchKernelGGL(k_classify, dim3(std::min(gj, 4 * cus)), dim3(1024), 0, s, W, l, Tn, P.levels);
+    if (l == 1) prof_begin(TTV_PROF_SCATTER1, s);
     hipLaunchKernelGGL((k_scatter<IdxT, F, PM>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
+    if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_pure<F>, dim3(2 * cus), dim3(256), 0, s, W);
   hipLaunchKernelGGL(k_bm_a, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
   hipLaunchKernelGGL(k_bm_b, dim3(1), dim3(1024), 0, s, W);
   hipLaunchKernelGGL(k_rank, dim3(2 * cus), dim3(256), 0, s, W);
+  prof_begin(TTV_PROF_FINISH, s);
   hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(2 * cus), dim3(kFinishThreads), 0, s, W, P.spin_limit);
+  prof_end(TTV_PROF_FINISH, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_last_hip_error((int)e);
