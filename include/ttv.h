@@ -59,7 +59,7 @@ enum {
   TTV_E_MODE = -3,      /* mode / kept mode out of range, or repeated */
   TTV_E_SHAPE = -4,     /* a dimension < 1, or a vector length != its dimension */
   TTV_E_DTYPE = -5,     /* unknown index/value type, or mixed types in a batch */
-  TTV_E_KEYBITS = -6,   /* the remaining-mode indices need more than 64 key bits */
+  TTV_E_KEYBITS = -6,   /* the product of the remaining dimensions exceeds 2^64 */
   TTV_E_WORKSPACE = -7, /* workspace null or smaller than the query says */
   TTV_E_INDEX = -8,     /* (device) an index was out of range (TTV_VALIDATE) */
   TTV_E_HIP = -9,       /* a HIP runtime call failed: see ttv_last_hip_error */
@@ -105,8 +105,8 @@ typedef struct {
 typedef struct {
   int32_t order, nrem, key_bits, levels;
   int32_t rem_modes[TTV_MAX_ORDER]; /* remaining modes, ascending */
-  int32_t bits[TTV_MAX_ORDER];      /* key bits of each remaining mode */
-  int32_t shift[TTV_MAX_ORDER];     /* bit position of each remaining mode */
+  int32_t bits[TTV_MAX_ORDER];      /* bits of each remaining mode's largest index */
+  int64_t stride[TTV_MAX_ORDER];    /* key = sum of index * stride over the remaining modes */
   int32_t digit1_bits;              /* bits of the first bucket level */
   int32_t reserved;
   int64_t workspace_bytes;
@@ -124,9 +124,10 @@ int ttv_last_hip_error(void);
 /*
  * Host-only planning of the product that contracts the modes in `modes`
  * (ncon entries, distinct): which modes remain, how their indices pack into
- * a sort key (first remaining mode most significant, so numeric key order is
- * lexicographic order -- the `unique` step of Sec. 3.3), how many bucket
- * levels the key needs, and the workspace size.  Touches no device.
+ * a mixed-radix sort key (first remaining mode most significant, so numeric
+ * key order is lexicographic order -- the `unique` step of Sec. 3.3; the key
+ * range is the product of the remaining dimensions), how many bucket levels
+ * the key needs, and the workspace size.  Touches no device.
  */
 int ttv_plan_query(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes,
                    int32_t flags, ttv_plan_info* out);

@@ -31,7 +31,7 @@ class CooDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("order", c_int32), ("nrem", c_int32), ("key_bits", c_int32), ("levels", c_int32),
-        ("rem_modes", c_int32 * MAX_ORDER), ("bits", c_int32 * MAX_ORDER), ("shift", c_int32 * MAX_ORDER),
+        ("rem_modes", c_int32 * MAX_ORDER), ("bits", c_int32 * MAX_ORDER), ("stride", c_int64 * MAX_ORDER),
         ("digit1_bits", c_int32), ("reserved", c_int32), ("workspace_bytes", c_int64),
     ]
 

@@ -58,6 +58,33 @@ static int bitlen(unsigned long long x) {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Division of 64-bit keys by an invariant divisor d >= 1 (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994):
+// with l = ceil(log2 d) and m = floor(2^64 (2^l - d) / d) + 1,
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = mulhi(m, n).
+void set_divmagic(unsigned long long d, unsigned long long& m, int& sh1, int& sh2) {
+  int l = 0;
+  while (l < 64 && ((unsigned __int128)1 << l) < (unsigned __int128)d) ++l;
+  const unsigned __int128 two_l = (unsigned __int128)1 << l;
+  m = (unsigned long long)(((two_l - d) << 64) / d + 1);
+  sh1 = l < 1 ? l : 1;
+  sh2 = l > 1 ? l - 1 : 0;
+}
+
+// First-level digit: the smallest width (<= kRMax) whose used digits leave
+// about 0.6 * kSmall nonzeros per bucket on uniform keys.
+int choose_r1(long long nnz, unsigned __int128 range, int bits) {
+  const double target = 0.6 * kSmall;
+  int r1 = 0;
+  while (r1 < kRMax && r1 < bits) {
+    const int shift = bits - r1;
+    const double used = (double)((range + (((unsigned __int128)1 << shift) - 1)) >> shift);
+    if ((double)nnz / used <= target) break;
+    ++r1;
+  }
+  return r1;
+}
+
 // Validates a descriptor and fills the tensor part of a TDesc: remaining
 // modes (all modes minus the contracted ones, ascending -- the set
 // difference of Sec. 3.3), their key fields (first remaining mode most
@@ -101,35 +128,26 @@ int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
   }
   D.nrem = nr;
   D.ncon = nc;
-  int bits = 0;
-  for (int i = 0; i < nr; ++i) {
-    D.width[i] = bitlen((unsigned long long)(X->shape[D.rem[i]] - 1));
-    bits += D.width[i];
-  }
-  if (bits > 64) return TTV_E_KEYBITS;
-  D.keybits = bits;
-  int sh = 0;
+  // mixed-radix key over the remaining modes (first remaining mode most
+  // significant): numeric order = lexicographic order of the index tuples
+  unsigned __int128 range = 1;
   for (int i = nr - 1; i >= 0; --i) {
-    D.shift[i] = sh;
-    sh += D.width[i];
+    D.kstride[i] = (unsigned long long)range;
+    range *= (unsigned __int128)X->shape[D.rem[i]];
+    if (range > ((unsigned __int128)1 << 64)) return TTV_E_KEYBITS;
   }
+  for (int i = 0; i < nr; ++i) set_divmagic(D.kstride[i], D.kmagic[i], D.ksh1[i], D.ksh2[i]);
   for (int j = 0; j < TTV_MAX_ORDER; ++j) {
-    D.mshift[j] = -1;
-    D.mwidth[j] = 0;
+    D.mstride[j] = 0;
+    D.mrem[j] = 0;
   }
   for (int i = 0; i < nr; ++i) {
-    D.mshift[D.rem[i]] = D.shift[i];
-    D.mwidth[D.rem[i]] = D.width[i];
+    D.mstride[D.rem[i]] = D.kstride[i];
+    D.mrem[D.rem[i]] = 1;
   }
-  // first digit: expected bucket about 0.6 * kSmall records
-  int r1 = 0;
-  const double target = 0.6 * kSmall;
-  while (r1 < kRMax && r1 < bits && (double)X->nnz / (double)(1LL << r1) > target) ++r1;
-  D.r1 = r1;
-  int nd = 0;
-  for (int i = 0; i < nr; ++i)
-    if (D.shift[i] + D.width[i] > bits - r1 && D.width[i] > 0) nd = i + 1;
-  D.ndig_modes = r1 > 0 ? nd : 0;
+  const int bits = bitlen((unsigned long long)(range - 1));
+  D.keybits = bits;
+  D.r1 = choose_r1(X->nnz, range, bits);
   D.validate = (flags & TTV_VALIDATE) ? 1 : 0;
   D.out_f64 = (flags & TTV_OUT_F64) ? 1 : 0;
   form = X->value_dtype == TTV_F64 ? kF64 : kC32;
@@ -219,7 +237,7 @@ const char* ttv_strerror(int s) {
     case TTV_E_MODE: return "mode out of range or repeated";
     case TTV_E_SHAPE: return "invalid dimension or vector length";
     case TTV_E_DTYPE: return "unsupported or mixed index/value type";
-    case TTV_E_KEYBITS: return "remaining-mode indices need more than 64 key bits";
+    case TTV_E_KEYBITS: return "the product of the remaining dimensions exceeds 2^64";
     case TTV_E_WORKSPACE: return "workspace missing or too small";
     case TTV_E_INDEX: return "an index is out of range";
     case TTV_E_HIP: return "a HIP runtime call failed";
@@ -247,8 +265,8 @@ int ttv_plan_query(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, in
   out->levels = P.levels;
   for (int i = 0; i < P.d0.nrem; ++i) {
     out->rem_modes[i] = P.d0.rem[i];
-    out->bits[i] = P.d0.width[i];
-    out->shift[i] = P.d0.shift[i];
+    out->bits[i] = bitlen((unsigned long long)(X->shape[P.d0.rem[i]] - 1));
+    out->stride[i] = (int64_t)P.d0.kstride[i];
   }
   out->digit1_bits = P.d0.r1;
   out->workspace_bytes = (int64_t)P.L.end;

@@ -62,10 +62,6 @@ void apply_tuning(ttv_batch_plan* p, const Tuning& t) {
     int r1 = std::min(std::max(p->base_r1[i] + t.r1_bias, 0), std::min(kRMax, D.keybits));
     if (p->base_r1[i] == 0) r1 = 0;  // tiny tensors stay a single bucket
     D.r1 = r1;
-    int nd = 0;
-    for (int q = 0; q < D.nrem; ++q)
-      if (D.shift[q] + D.width[q] > D.keybits - r1 && D.width[q] > 0) nd = q + 1;
-    D.ndig_modes = r1 > 0 ? nd : 0;
     const int rest = std::max(0, D.keybits - r1);
     levels = std::max(levels, std::min(kMaxLevels, 1 + (rest + kRMax - 1) / kRMax));
     tiles1 += (D.nnz + P.T1 - 1) / P.T1;

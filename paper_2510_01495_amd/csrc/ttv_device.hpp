@@ -238,6 +238,14 @@ __device__ __forceinline__ long long ld_idx(const TDesc& D, long long e, int j) 
 
 __device__ __forceinline__ void set_error(Ctrl* C, int code) { atomicCAS(&C->error, 0, code); }
 
+// n / d for an invariant divisor d, from its magic multiplier (see the
+// planner): t = mulhi(m, n), q = (t + ((n - t) >> sh1)) >> sh2.
+__device__ __forceinline__ unsigned long long udiv_magic(unsigned long long n, unsigned long long m, int sh1,
+                                                         int sh2) {
+  const unsigned long long t = __umul64hi(m, n);
+  return (t + ((n - t) >> sh1)) >> sh2;
+}
+
 __device__ __forceinline__ int bitlen64(unsigned long long x) { return x ? 64 - __clzll((long long)x) : 0; }
 
 }  // namespace ttv

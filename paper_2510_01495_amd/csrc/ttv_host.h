@@ -36,6 +36,8 @@ int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
 Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1);
 int finish_plan(PipePlan& P);  // levels, tiles and layout of a planned single tensor
 int launch_zero(void* p, size_t bytes, hipStream_t s);
+void set_divmagic(unsigned long long d, unsigned long long& m, int& sh1, int& sh2);
+int choose_r1(long long nnz, unsigned __int128 range, int bits);
 
 // measurement hook (see ttv_profile_events)
 void prof_begin(int kernel, hipStream_t s);

@@ -19,13 +19,13 @@ constexpr int kWave = 64;
 constexpr int kMaxOrder = TTV_MAX_ORDER;
 constexpr int kRMax = 12;                // digit bits per bucket level
 constexpr int kNDig = 1 << kRMax;        // row stride of the per-tile digit tables
-constexpr int kCap = 8192;               // most records an LDS leaf holds
+constexpr int kCap = 4096;               // most records an LDS leaf holds
 constexpr int kSmall = kCap / 2;         // buckets up to this size are merged into chunks
 constexpr int kMaxLevels = 8;            // 64-bit keys with 12-bit digits need at most 6
 constexpr int kPureTile = 16384;         // records per block when reducing a single-key bucket
 constexpr int kScatterThreads = 256;     // 4 waves
 constexpr int kScatterIPT = 8;           // records per thread per round
-constexpr int kFinishThreads = 512;      // 8 waves
+constexpr int kFinishThreads = 512;     // 8 waves
 constexpr int kFinishIPT = kCap / kFinishThreads;
 constexpr int kSortDigit = 8;            // LDS radix digit width
 
@@ -69,13 +69,17 @@ struct TDesc {
   int32_t ncon;                 // contracted modes
   int32_t keybits;
   int32_t rem[kMaxOrder];       // remaining modes, ascending; rem[0] is most significant
-  int32_t shift[kMaxOrder];     // bit position of each remaining mode's field
-  int32_t width[kMaxOrder];
   int32_t con[kMaxOrder];       // contracted modes, ascending
-  int32_t mshift[kMaxOrder];    // per mode: key shift of a remaining mode, -1 if contracted
-  int32_t mwidth[kMaxOrder];    // per mode: key bits of a remaining mode
+  // Keys are mixed-radix: key = sum_i idx(rem[i]) * kstride[i], kstride[nrem-1] = 1,
+  // kstride[i] = kstride[i+1] * dims[rem[i+1]] -- dense, and ordered like the tuples.
+  unsigned long long kstride[kMaxOrder];
+  unsigned long long kmagic[kMaxOrder];  // key / kstride[i] by multiply-high (invariant divisor)
+  int32_t ksh1[kMaxOrder];
+  int32_t ksh2[kMaxOrder];
+  unsigned long long mstride[kMaxOrder];  // per mode: key stride of a remaining mode
+  int32_t mrem[kMaxOrder];                // per mode: 1 if the mode remains in the key
   int32_t r1;                   // digit bits of the first level
-  int32_t ndig_modes;           // leading remaining modes that overlap the first digit
+  int32_t pad0;
   int32_t out_f64;              // compensated form writes FP64 values
   int32_t validate;             // check every index against dims
 };

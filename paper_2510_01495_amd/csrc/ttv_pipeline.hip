@@ -63,9 +63,6 @@ __device__ __forceinline__ int dst_of(int level) { return (level & 1) ? kSrcA : 
 __device__ __forceinline__ bool aborted(const Ctrl* C) { return C->error == TTV_E_DEVICE; }
 __device__ __forceinline__ int clampi(long long v, long long cap) { return (int)(v < cap ? v : cap); }
 
-__device__ __forceinline__ long long field(long long x, int width) {
-  return x & (long long)((width >= 63) ? ~0ull >> 1 : ((1ull << width) - 1ull));
-}
 
 #ifdef TTV_PHASE_PROFILE
 // Build-time option for kernel phase timing (wall clock, 100 MHz ticks).
@@ -113,8 +110,8 @@ struct RawSrc {
   const In* vec[kMaxOrder];
   long long sj[kMaxOrder];
   long long dim[kMaxOrder];
-  int shift[kMaxOrder];  // key shift of a remaining mode, -1 otherwise
-  int width[kMaxOrder];
+  unsigned long long kst[kMaxOrder];  // key stride of a remaining mode
+  int rem[kMaxOrder];                 // 1 if the mode remains in the key
   const In* segfac;
   const int32_t* segidx;
   __device__ __forceinline__ void set(const TDesc& D) {
@@ -129,8 +126,8 @@ struct RawSrc {
       vec[m] = static_cast<const In*>(D.vec[m]);
       sj[m] = (long long)m * D.stride_j;
       dim[m] = D.dims[m];
-      shift[m] = D.mshift[m];
-      width[m] = D.mwidth[m];
+      kst[m] = D.mstride[m];
+      rem[m] = D.mrem[m];
     }
   }
 };
@@ -160,8 +157,8 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e
   const int order = S.order;
   const bool validate = S.validate != 0;
   for (int m = 0; m < order; ++m) {
-    const int sh = S.shift[m];
-    if (sh < 0 && (PM == kPipeSegMap || !S.vec[m])) continue;
+    const bool isrem = S.rem[m] != 0;
+    if (!isrem && (PM == kPipeSegMap || !S.vec[m])) continue;
     const long long sj = S.sj[m];
     long long x[IPT];
 #pragma unroll
@@ -178,10 +175,10 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e
           x[j] = 0;
         }
     }
-    if (sh >= 0) {
-      const int wd = S.width[m];
+    if (isrem) {
+      const unsigned long long st = S.kst[m];
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) key[j] |= (uint64_t)field(x[j], wd) << sh;
+      for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[j] * st;
     } else if (S.vec[m]) {
       const gptr<const In> vec = to_global(S.vec[m]);
       In g[IPT];
@@ -316,8 +313,9 @@ __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
         const long long e0 = J.start - D.base + b + i0;
 #pragma unroll
         for (int j = 0; j < IPT; ++j) key[j] = 0;
-        for (int q = 0; q < D.ndig_modes; ++q) {
-          const int m = D.rem[q];
+        for (int m = 0; m < D.order; ++m) {
+          if (!D.mrem[m]) continue;
+          const unsigned long long st = D.mstride[m];
           long long x[IPT];
 #pragma unroll
           for (int j = 0; j < IPT; ++j)
@@ -325,7 +323,7 @@ __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
             if (D.validate && (x[j] < 0 || x[j] >= D.dims[m])) x[j] = 0;
-            key[j] |= (uint64_t)field(x[j], D.width[q]) << D.shift[q];
+            key[j] += (uint64_t)x[j] * st;
           }
         }
       } else {
@@ -863,8 +861,10 @@ struct OutInfo {
   gptr<float> v32;
   int nrem;
   int f64out;
-  int shift[kMaxOrder];
-  unsigned long long mask[kMaxOrder];
+  unsigned long long kst[kMaxOrder];
+  unsigned long long mag[kMaxOrder];
+  int sh1[kMaxOrder];
+  int sh2[kMaxOrder];
   __device__ __forceinline__ void load(const TDesc& D) {
     subs = to_global(static_cast<IdxT*>(D.out_subs));
     v64 = to_global(static_cast<double*>(D.out_vals));
@@ -873,15 +873,24 @@ struct OutInfo {
     f64out = (F == kF64) || D.out_f64;
 #pragma unroll
     for (int i = 0; i < kMaxOrder; ++i) {
-      shift[i] = D.shift[i];
-      mask[i] = D.width[i] >= 64 ? ~0ull : ((1ull << D.width[i]) - 1ull);
+      kst[i] = D.kstride[i];
+      mag[i] = D.kmagic[i];
+      sh1[i] = D.ksh1[i];
+      sh2[i] = D.ksh2[i];
     }
   }
+  // unpack the mixed-radix key into the remaining indices, then the value
   __device__ __forceinline__ void write(long long row, uint64_t key, double v) const {
     gptr<IdxT> o = subs + row * nrem;
-#pragma unroll
-    for (int i = 0; i < kMaxOrder; ++i)
-      if (i < nrem) o[i] = (IdxT)((key >> shift[i]) & mask[i]);
+    unsigned long long k = key;
+    // kept rolled: the constants stay in LDS instead of pinning registers
+#pragma unroll 1
+    for (int i = 0; i < nrem - 1; ++i) {
+      const unsigned long long q = udiv_magic(k, mag[i], sh1[i], sh2[i]);
+      o[i] = (IdxT)q;
+      k -= q * kst[i];
+    }
+    o[nrem - 1] = (IdxT)k;  // the last stride is 1
     if (f64out)
       v64[row] = v;
     else
