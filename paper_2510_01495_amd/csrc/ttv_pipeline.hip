@@ -133,69 +133,127 @@ struct RawSrc {
 };
 
 // One round of IPT records per lane: item j of this lane is nonzero
-// e0 + j*64 (valid while j*64 < n_left).  Loads are issued per mode for all
-// items at once.
-template <typename IdxT, int F, int PM, int IPT>
-__device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e0, long long n_left, Ctrl* C,
-                                           uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
+// e0 + j*64 (valid while j*64 < n_left).  MO >= order: every index column of
+// the round is loaded before any is used (one memory round trip), then the
+// vector entries of the contracted modes are gathered (a second one).
+template <typename IdxT, int F, int PM, int IPT, int MO>
+__device__ __forceinline__ void load_round_mo(const RawSrc<IdxT, F>& S, long long e0, long long n_left, Ctrl* C,
+                                              uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
   using FO = FormOps<F>;
   using In = typename FO::In;
   const gptr<const In> vals = to_global(S.vals);
   const gptr<const IdxT> subs = to_global(S.subs);
   const long long se = S.se;
+  const int order = S.order;
+  In a[IPT];
+  long long x[MO][IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const bool ok = (long long)j * 64 < n_left;
+    const long long e = e0 + (long long)j * 64;
+    a[j] = (PM != kPipeSegMap && ok) ? vals[e] : (In)0;
+#pragma unroll
+    for (int m = 0; m < MO; ++m) x[m][j] = (m < order && ok) ? (long long)subs[e * se + S.sj[m]] : 0;
+  }
+  if (S.validate) {
+#pragma unroll
+    for (int m = 0; m < MO; ++m)
+#pragma unroll
+      for (int j = 0; j < IPT; ++j)
+        if (m < order && (long long)j * 64 < n_left && (x[m][j] < 0 || x[m][j] >= S.dim[m])) {
+          set_error(C, TTV_E_INDEX);
+          x[m][j] = 0;
+        }
+  }
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     key[j] = 0;
-    pay[j] = 0;
-    if ((long long)j * 64 < n_left) {
-      if (PM == kPipeSegMap)
-        pay[j] = (uint64_t)(e0 + (long long)j * 64);
-      else
-        pay[j] = FO::start_prod(vals[e0 + (long long)j * 64]);
+    pay[j] = PM == kPipeSegMap ? (uint64_t)(e0 + (long long)j * 64) : FO::start_prod(a[j]);
+  }
+#pragma unroll
+  for (int m = 0; m < MO; ++m) {
+    if (m >= order) break;
+    if (S.rem[m]) {
+      const unsigned long long st = S.kst[m];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[m][j] * st;
     }
   }
-  const int order = S.order;
-  const bool validate = S.validate != 0;
-  for (int m = 0; m < order; ++m) {
-    const bool isrem = S.rem[m] != 0;
-    if (!isrem && (PM == kPipeSegMap || !S.vec[m])) continue;
-    const long long sj = S.sj[m];
-    long long x[IPT];
+  if (PM == kPipeSegMap) return;
+  // gathers of the contracted modes' vector entries (issued together)
+  In g[MO][IPT];
+#pragma unroll
+  for (int m = 0; m < MO; ++m) {
+    const bool use = m < order && !S.rem[m] && S.vec[m] != nullptr;
+    const gptr<const In> vec = to_global(S.vec[m < kMaxOrder ? m : 0]);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) g[m][j] = (use && (long long)j * 64 < n_left) ? vec[x[m][j]] : (In)1;
+  }
+#pragma unroll
+  for (int m = 0; m < MO; ++m) {
+    if (m >= order) break;
+    if (!S.rem[m] && S.vec[m]) {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[m][j]);
+    }
+  }
+  if (S.segfac) {
+    const gptr<const In> sf = to_global(S.segfac);
+    const gptr<const int32_t> sx = to_global(S.segidx);
+    In h[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) h[j] = ((long long)j * 64 < n_left) ? sf[sx[e0 + (long long)j * 64]] : (In)0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], h[j]);
+  }
+}
+
+template <typename IdxT, int F, int PM, int IPT>
+__device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e0, long long n_left, Ctrl* C,
+                                           uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
+  if (S.order <= 3) {
+    load_round_mo<IdxT, F, PM, IPT, 3>(S, e0, n_left, C, key, pay);
+  } else if (S.order <= 5) {
+    load_round_mo<IdxT, F, PM, IPT, 5>(S, e0, n_left, C, key, pay);
+  } else {  // orders 6-8: one mode at a time (keeps the register footprint of the common orders)
+    using FO = FormOps<F>;
+    using In = typename FO::In;
+    const gptr<const In> vals = to_global(S.vals);
+    const gptr<const IdxT> subs = to_global(S.subs);
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-      x[j] = 0;
-      if ((long long)j * 64 < n_left) x[j] = (long long)subs[(e0 + (long long)j * 64) * se + sj];
+      const bool ok = (long long)j * 64 < n_left;
+      const long long e = e0 + (long long)j * 64;
+      key[j] = 0;
+      pay[j] = PM == kPipeSegMap ? (uint64_t)e : FO::start_prod(ok ? vals[e] : (In)0);
     }
-    if (validate) {
-      const long long dim = S.dim[m];
+    for (int m = 0; m < S.order; ++m) {
+      if (!S.rem[m] && (PM == kPipeSegMap || !S.vec[m])) continue;
+      long long x[IPT];
 #pragma unroll
-      for (int j = 0; j < IPT; ++j)
-        if ((long long)j * 64 < n_left && (x[j] < 0 || x[j] >= dim)) {
+      for (int j = 0; j < IPT; ++j) {
+        x[j] = ((long long)j * 64 < n_left) ? (long long)subs[(e0 + (long long)j * 64) * S.se + S.sj[m]] : 0;
+        if (S.validate && (long long)j * 64 < n_left && (x[j] < 0 || x[j] >= S.dim[m])) {
           set_error(C, TTV_E_INDEX);
           x[j] = 0;
         }
+      }
+      if (S.rem[m]) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[j] * S.kst[m];
+      } else {
+        const gptr<const In> vec = to_global(S.vec[m]);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], ((long long)j * 64 < n_left) ? vec[x[j]] : (In)0);
+      }
     }
-    if (isrem) {
-      const unsigned long long st = S.kst[m];
+    if (PM != kPipeSegMap && S.segfac) {
+      const gptr<const In> sf = to_global(S.segfac);
+      const gptr<const int32_t> sx = to_global(S.segidx);
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[j] * st;
-    } else if (S.vec[m]) {
-      const gptr<const In> vec = to_global(S.vec[m]);
-      In g[IPT];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) g[j] = ((long long)j * 64 < n_left) ? vec[x[j]] : (In)0;
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[j]);
+      for (int j = 0; j < IPT; ++j)
+        pay[j] = FO::mul_prod(pay[j], ((long long)j * 64 < n_left) ? sf[sx[e0 + (long long)j * 64]] : (In)0);
     }
-  }
-  if (PM != kPipeSegMap && S.segfac) {
-    const gptr<const In> sf = to_global(S.segfac);
-    const gptr<const int32_t> sx = to_global(S.segidx);
-    In g[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) g[j] = ((long long)j * 64 < n_left) ? sf[sx[e0 + (long long)j * 64]] : (In)0;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[j]);
   }
 }
 
@@ -838,10 +896,16 @@ __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit,
           s = kFlagInc;
           break;
         }
+#ifdef TTV_PHASE_PROFILE
+        atomicAdd(&g_phase[9], 1ull);
+#endif
         __builtin_amdgcn_s_sleep(1);
       }
     }
     const uint64_t pm = ballot((s >> 62) == 2);
+#ifdef TTV_PHASE_PROFILE
+    if (ln == 0) atomicAdd(&g_phase[8], 1ull);
+#endif
     const int stop = pm ? __ffsll((long long)pm) - 1 : 63;
     long long v = ((int)ln <= stop) ? (long long)(s & kValMask) : 0;
 #pragma unroll
