@@ -21,6 +21,14 @@ __device__ __forceinline__ unsigned count_below(uint64_t m) {
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Orders LDS accesses of one wave across lanes (a wave's LDS instructions
+// execute in issue order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lanes of `valid` whose r-bit digit equals this lane's (ballot multisplit:
 // one ballot per digit bit, keep the lanes that agree on every bit).
 __device__ __forceinline__ uint64_t match_digit(unsigned d, int r, uint64_t valid) {

@@ -24,6 +24,8 @@ constexpr int kSmall = kCap / 2;         // buckets up to this size are merged i
 constexpr int kMaxLevels = 8;            // 64-bit keys with 12-bit digits need at most 6
 constexpr int kPureTile = 16384;         // records per block when reducing a single-key bucket
 constexpr int kScatterThreads = 256;     // 4 waves
+constexpr int kHistThreads = 1024;       // 16 waves
+constexpr int kHistIPT = 4;
 constexpr int kScatterIPT = 8;           // records per thread per round
 constexpr int kFinishThreads = 512;     // 8 waves
 constexpr int kFinishIPT = kCap / kFinishThreads;

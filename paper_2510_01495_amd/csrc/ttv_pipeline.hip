@@ -96,71 +96,140 @@ constexpr int kBitmapWordsPerBlock = 8192;  // 256 threads x 32 words
 // first remaining mode most significant; payload = value times the vector
 // entries of the contracted modes (ascending), or the nonzero's index.
 // ---------------------------------------------------------------------------
-// What a tile needs to read nonzeros of one tensor, staged in LDS once per
-// tile (descriptor fields read from global memory would be re-fetched after
-// every store).
-template <typename IdxT, int F>
+// What a tile needs to read nonzeros of one tensor, copied once per tile
+// from the (wave-uniform) descriptor into registers: fields left in memory
+// would be loaded again after every barrier or fence of the round loop.
+template <typename IdxT, int F, int MO>
 struct RawSrc {
   using In = typename FormOps<F>::In;
   const IdxT* subs;
   const In* vals;
   long long se;
+  long long sj;        // stride between the indices of one nonzero
   int order;
   int validate;
-  const In* vec[kMaxOrder];
-  long long sj[kMaxOrder];
-  long long dim[kMaxOrder];
-  unsigned long long kst[kMaxOrder];  // key stride of a remaining mode
-  int rem[kMaxOrder];                 // 1 if the mode remains in the key
+  int rowmajor;        // rows of se <= kMaxOrder consecutive indices: read whole rows, coalesced
+  unsigned remmask;    // bit m: mode m remains in the key
+  const In* vec[MO];
+  long long dim[MO];
+  unsigned long long kst[MO];  // key stride of a remaining mode
   const In* segfac;
   const int32_t* segidx;
+  __device__ __forceinline__ bool rem(int m) const { return (remmask >> m) & 1u; }
   __device__ __forceinline__ void set(const TDesc& D) {
     subs = static_cast<const IdxT*>(D.subs);
     vals = static_cast<const In*>(D.vals);
     segfac = static_cast<const In*>(D.segfac);
     segidx = D.segidx;
     se = D.stride_e;
+    sj = D.stride_j;
     order = D.order;
     validate = D.validate;
-    for (int m = 0; m < kMaxOrder; ++m) {
+    rowmajor = (D.order == 1 || D.stride_j == 1) && D.stride_e >= D.order && D.stride_e <= kMaxOrder;
+    remmask = 0;
+#pragma unroll
+    for (int m = 0; m < MO; ++m) {
       vec[m] = static_cast<const In*>(D.vec[m]);
-      sj[m] = (long long)m * D.stride_j;
       dim[m] = D.dims[m];
       kst[m] = D.mstride[m];
-      rem[m] = D.mrem[m];
+      remmask |= (D.mrem[m] ? 1u : 0u) << m;
     }
   }
 };
 
-// One round of IPT records per lane: item j of this lane is nonzero
-// e0 + j*64 (valid while j*64 < n_left).  MO >= order: every index column of
-// the round is loaded before any is used (one memory round trip), then the
-// vector entries of the contracted modes are gathered (a second one).
+// The index columns of one round: item j of this lane is nonzero
+// r0 + j*64 + lane, valid while j*64 + lane < nrec (r0 is the first nonzero of
+// the wave's slice).  x[m][j] holds mode m's index (0 for m >= order or an
+// invalid item).
+//   Row-major rows (se consecutive indices per nonzero): the wave reads its
+//   slice as consecutive words (every lane one word per load, so a load covers
+//   whole cache lines) and transposes 64 rows at a time through its LDS stage
+//   (64*MO words).  A lane reading its own row directly would touch 64 rows'
+//   worth of lines per load for one index each, which caps the read rate well
+//   below HBM bandwidth.
+//   Other strides (structure of arrays): one load per mode, lane-consecutive.
+template <typename IdxT, int F, int IPT, int MO, typename Fn>
+__device__ __forceinline__ void for_cols(const RawSrc<IdxT, F, MO>& S, long long r0, long long nrec, IdxT* stage,
+                                         Fn&& f) {
+  const gptr<const IdxT> subs = to_global(S.subs);
+  const unsigned ln = lane_id();
+  const int order = S.order;
+  const long long se = S.se;
+  if (S.rowmajor) {
+    const long long nr = nrec <= 0 ? 0 : (nrec < 64 * IPT ? nrec : 64 * IPT);
+    const long long wend = nr ? (nr - 1) * se + order : 0;  // the last row's padding is not read
+    const gptr<const IdxT> p = subs + r0 * se;
+    IdxT raw[IPT][MO];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+#pragma unroll
+      for (int c = 0; c < MO; ++c) {
+        const long long wi = (long long)j * 64 * se + c * 64 + ln;
+        raw[j][c] = (c < se && wi < wend) ? p[wi] : (IdxT)0;
+      }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      wave_lds_sync();
+#pragma unroll
+      for (int c = 0; c < MO; ++c)
+        if (c < se) stage[c * 64 + ln] = raw[j][c];
+      wave_lds_sync();
+#pragma unroll
+      for (int m = 0; m < MO; ++m)
+        if (m < order) f(m, j, (long long)stage[ln * se + m]);
+    }
+    wave_lds_sync();
+  } else {
+#pragma unroll
+    for (int m = 0; m < MO; ++m) {
+      if (m >= order) break;
+      long long x[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const long long i = (long long)j * 64 + ln;
+        x[j] = i < nrec ? (long long)subs[(r0 + i) * se + (long long)m * S.sj] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) f(m, j, x[j]);
+    }
+  }
+}
+
+template <typename IdxT, int F, int IPT, int MO>
+__device__ __forceinline__ void fetch_cols(const RawSrc<IdxT, F, MO>& S, long long r0, long long nrec, IdxT* stage,
+                                           long long (&x)[MO][IPT]) {
+#pragma unroll
+  for (int m = 0; m < MO; ++m)
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) x[m][j] = 0;
+  for_cols<IdxT, F, IPT, MO>(S, r0, nrec, stage, [&](int m, int j, long long v) { x[m][j] = v; });
+}
+
+// One round of IPT records per lane (as fetch_cols): key and payload.  The
+// index columns come in first, then the vector entries of the contracted modes
+// are gathered together (a second memory round trip).
 template <typename IdxT, int F, int PM, int IPT, int MO>
-__device__ __forceinline__ void load_round_mo(const RawSrc<IdxT, F>& S, long long e0, long long n_left, Ctrl* C,
-                                              uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
+__device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long long r0, long long nrec, IdxT* stage,
+                                           Ctrl* C, uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
   using FO = FormOps<F>;
   using In = typename FO::In;
   const gptr<const In> vals = to_global(S.vals);
-  const gptr<const IdxT> subs = to_global(S.subs);
-  const long long se = S.se;
+  const unsigned ln = lane_id();
   const int order = S.order;
   In a[IPT];
-  long long x[MO][IPT];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
-    const bool ok = (long long)j * 64 < n_left;
-    const long long e = e0 + (long long)j * 64;
-    a[j] = (PM != kPipeSegMap && ok) ? vals[e] : (In)0;
-#pragma unroll
-    for (int m = 0; m < MO; ++m) x[m][j] = (m < order && ok) ? (long long)subs[e * se + S.sj[m]] : 0;
+    const long long i = (long long)j * 64 + ln;
+    a[j] = (PM != kPipeSegMap && i < nrec) ? vals[r0 + i] : (In)0;
   }
+  long long x[MO][IPT];
+  fetch_cols<IdxT, F, IPT, MO>(S, r0, nrec, stage, x);
   if (S.validate) {
 #pragma unroll
     for (int m = 0; m < MO; ++m)
 #pragma unroll
       for (int j = 0; j < IPT; ++j)
-        if (m < order && (long long)j * 64 < n_left && (x[m][j] < 0 || x[m][j] >= S.dim[m])) {
+        if (m < order && (long long)j * 64 + ln < nrec && (x[m][j] < 0 || x[m][j] >= S.dim[m])) {
           set_error(C, TTV_E_INDEX);
           x[m][j] = 0;
         }
@@ -168,31 +237,30 @@ __device__ __forceinline__ void load_round_mo(const RawSrc<IdxT, F>& S, long lon
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     key[j] = 0;
-    pay[j] = PM == kPipeSegMap ? (uint64_t)(e0 + (long long)j * 64) : FO::start_prod(a[j]);
+    pay[j] = PM == kPipeSegMap ? (uint64_t)(r0 + (long long)j * 64 + ln) : FO::start_prod(a[j]);
   }
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
     if (m >= order) break;
-    if (S.rem[m]) {
+    if (S.rem(m)) {
       const unsigned long long st = S.kst[m];
 #pragma unroll
       for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[m][j] * st;
     }
   }
   if (PM == kPipeSegMap) return;
-  // gathers of the contracted modes' vector entries (issued together)
   In g[MO][IPT];
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
-    const bool use = m < order && !S.rem[m] && S.vec[m] != nullptr;
-    const gptr<const In> vec = to_global(S.vec[m < kMaxOrder ? m : 0]);
+    const bool use = m < order && !S.rem(m) && S.vec[m] != nullptr;
+    const gptr<const In> vec = to_global(S.vec[m]);
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) g[m][j] = (use && (long long)j * 64 < n_left) ? vec[x[m][j]] : (In)1;
+    for (int j = 0; j < IPT; ++j) g[m][j] = (use && (long long)j * 64 + ln < nrec) ? vec[x[m][j]] : (In)1;
   }
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
     if (m >= order) break;
-    if (!S.rem[m] && S.vec[m]) {
+    if (!S.rem(m) && S.vec[m]) {
 #pragma unroll
       for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], g[m][j]);
     }
@@ -202,58 +270,12 @@ __device__ __forceinline__ void load_round_mo(const RawSrc<IdxT, F>& S, long lon
     const gptr<const int32_t> sx = to_global(S.segidx);
     In h[IPT];
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) h[j] = ((long long)j * 64 < n_left) ? sf[sx[e0 + (long long)j * 64]] : (In)0;
+    for (int j = 0; j < IPT; ++j) {
+      const long long i = (long long)j * 64 + ln;
+      h[j] = i < nrec ? sf[sx[r0 + i]] : (In)0;
+    }
 #pragma unroll
     for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], h[j]);
-  }
-}
-
-template <typename IdxT, int F, int PM, int IPT>
-__device__ __forceinline__ void load_round(const RawSrc<IdxT, F>& S, long long e0, long long n_left, Ctrl* C,
-                                           uint64_t (&key)[IPT], uint64_t (&pay)[IPT]) {
-  if (S.order <= 3) {
-    load_round_mo<IdxT, F, PM, IPT, 3>(S, e0, n_left, C, key, pay);
-  } else if (S.order <= 5) {
-    load_round_mo<IdxT, F, PM, IPT, 5>(S, e0, n_left, C, key, pay);
-  } else {  // orders 6-8: one mode at a time (keeps the register footprint of the common orders)
-    using FO = FormOps<F>;
-    using In = typename FO::In;
-    const gptr<const In> vals = to_global(S.vals);
-    const gptr<const IdxT> subs = to_global(S.subs);
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      const bool ok = (long long)j * 64 < n_left;
-      const long long e = e0 + (long long)j * 64;
-      key[j] = 0;
-      pay[j] = PM == kPipeSegMap ? (uint64_t)e : FO::start_prod(ok ? vals[e] : (In)0);
-    }
-    for (int m = 0; m < S.order; ++m) {
-      if (!S.rem[m] && (PM == kPipeSegMap || !S.vec[m])) continue;
-      long long x[IPT];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        x[j] = ((long long)j * 64 < n_left) ? (long long)subs[(e0 + (long long)j * 64) * S.se + S.sj[m]] : 0;
-        if (S.validate && (long long)j * 64 < n_left && (x[j] < 0 || x[j] >= S.dim[m])) {
-          set_error(C, TTV_E_INDEX);
-          x[j] = 0;
-        }
-      }
-      if (S.rem[m]) {
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[j] * S.kst[m];
-      } else {
-        const gptr<const In> vec = to_global(S.vec[m]);
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) pay[j] = FO::mul_prod(pay[j], ((long long)j * 64 < n_left) ? vec[x[j]] : (In)0);
-      }
-    }
-    if (PM != kPipeSegMap && S.segfac) {
-      const gptr<const In> sf = to_global(S.segfac);
-      const gptr<const int32_t> sx = to_global(S.segidx);
-#pragma unroll
-      for (int j = 0; j < IPT; ++j)
-        pay[j] = FO::mul_prod(pay[j], ((long long)j * 64 < n_left) ? sf[sx[e0 + (long long)j * 64]] : (In)0);
-    }
   }
 }
 
@@ -341,10 +363,15 @@ __device__ __forceinline__ void hist_add(unsigned* hist, unsigned d, bool valid)
 // ---------------------------------------------------------------------------
 // hist: per-tile digit counts -> table[tile][digit]
 // ---------------------------------------------------------------------------
-template <typename IdxT>
-__global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
-  constexpr int IPT = 16;
+// ---------------------------------------------------------------------------
+// hist: per-tile digit counts -> table[tile][digit]
+// ---------------------------------------------------------------------------
+template <typename IdxT, int MO>
+__global__ __launch_bounds__(kHistThreads) void k_hist(WsView W, int level, int T) {
+  constexpr int NT = kHistThreads;
+  constexpr int IPT = MO <= 3 ? kHistIPT : (MO <= 5 ? 3 : 2);  // rows per lane per round within 128 VGPRs
   __shared__ unsigned hist[kNDig];
+  __shared__ IdxT stage[NT / 64][64 * MO];
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int ntiles = clampi(C->ntiles[level], W.L.tcap);
@@ -357,37 +384,35 @@ __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
     const Job J = jobs[tj[t]];
     const int nd = 1 << J.r;
     const unsigned mask = (unsigned)nd - 1u;
-    for (int i = threadIdx.x; i < nd; i += 256) hist[i] = 0u;
+    for (int i = threadIdx.x; i < nd; i += NT) hist[i] = 0u;
+    const TDesc* Dp = W.desc() + J.tensor;
+    RawSrc<IdxT, kF64, MO> S;
+    S.set(*Dp);
     __syncthreads();
     const long long b = (long long)(t - J.tile0) * T;
     const long long n = (J.size - b < (long long)T) ? J.size - b : (long long)T;
-    // rounds of 256*IPT records; wave w takes a contiguous 64*IPT slice
-    for (long long rb = 0; rb < n; rb += 256 * IPT) {
-      const long long i0 = rb + (long long)w * 64 * IPT + ln;
+    const long long roff = J.start - Dp->base + b;
+    // keys of bucketed records: the first word of each 16-byte record
+    const gptr<const uint64_t> srcK = (J.src == kSrcRaw)
+                                          ? (gptr<const uint64_t>)nullptr
+                                          : to_global((const uint64_t*)W.rec(J.src)) + 2 * (J.start + b);
+    // rounds of NT*IPT records; wave w takes a contiguous 64*IPT slice
+    for (long long rb = 0; rb < n; rb += NT * IPT) {
+      const long long s0 = rb + (long long)w * 64 * IPT;
+      const long long i0 = s0 + ln;
       uint64_t key[IPT];
-      if (J.src == kSrcRaw) {
-        const TDesc& D = W.desc()[J.tensor];
-        const IdxT* subs = static_cast<const IdxT*>(D.subs);
-        const long long e0 = J.start - D.base + b + i0;
+      if (srcK) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) key[j] = (i0 + j * 64 < n) ? srcK[2 * (i0 + j * 64)] : 0;
+      } else {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) key[j] = 0;
-        for (int m = 0; m < D.order; ++m) {
-          if (!D.mrem[m]) continue;
-          const unsigned long long st = D.mstride[m];
-          long long x[IPT];
-#pragma unroll
-          for (int j = 0; j < IPT; ++j)
-            x[j] = (i0 + j * 64 < n) ? (long long)subs[(e0 + j * 64) * D.stride_e + (long long)m * D.stride_j] : 0;
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) {
-            if (D.validate && (x[j] < 0 || x[j] >= D.dims[m])) x[j] = 0;
-            key[j] += (uint64_t)x[j] * st;
-          }
-        }
-      } else {
-        const Rec* R = W.rec(J.src) + J.start + b;
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) key[j] = (i0 + j * 64 < n) ? R[i0 + j * 64].key : 0;
+        for_cols<IdxT, kF64, IPT, MO>(S, roff + s0, n - s0, stage[w], [&](int m, int j, long long v) {
+          if (!S.rem(m)) return;
+          // out-of-range indices count as 0 here; the scatter reports them
+          if (S.validate && (v < 0 || v >= S.dim[m])) v = 0;
+          key[j] += (uint64_t)v * S.kst[m];
+        });
       }
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
@@ -397,7 +422,7 @@ __global__ __launch_bounds__(256) void k_hist(WsView W, int level, int T) {
     }
     __syncthreads();
     unsigned* row = table + (size_t)t * kNDig;
-    for (int i = threadIdx.x; i < nd; i += 256) row[i] = hist[i];
+    for (int i = threadIdx.x; i < nd; i += NT) row[i] = hist[i];
     __syncthreads();
   }
 }
@@ -570,8 +595,42 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
       if (d < nd) s_nb[d] = nbq[q];
     }
     __syncthreads();
-    // emit jobs and leaves
+    // emit jobs and leaves; slots come from one block-wide reservation per
+    // counter (a per-bucket atomic on one address serialises thousands of
+    // buckets), handed out in digit order.
     const int dstb = dst_of(level);
+    const bool deeper = J.shift > 0 && level + 1 <= maxlevel;
+    unsigned c_lj = 0, c_tile = 0, c_pure = 0;  // c_lj: leaves (low 16 bits), jobs (high 16 bits)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int d = tid * 4 + q;
+      if (d >= nd || !bnd[q]) continue;
+      if (s_cls[d] == 3 && J.shift > 0) {
+        if (deeper) {
+          c_lj += 1u << 16;
+          c_tile += (unsigned)(((unsigned long long)sz[q] + Tnext - 1) / Tnext);
+        }
+      } else {
+        c_lj += 1u;
+        if (s_cls[d] == 3) c_pure += (unsigned)(((unsigned long long)sz[q] + kPureTile - 1) / kPureTile);
+      }
+    }
+    __shared__ long long s_base[4];
+    unsigned t_lj, t_tile, t_pure;
+    unsigned o_lj = block_excl_scan<1024>(c_lj, wsum, t_lj);
+    unsigned o_tile = block_excl_scan<1024>(c_tile, wsum, t_tile);
+    unsigned o_pure = block_excl_scan<1024>(c_pure, wsum, t_pure);
+    if (tid == 0) {
+      s_base[0] = (t_lj & 0xffffu) ? atomicAdd(&C->nleaves, (int)(t_lj & 0xffffu)) : 0;
+      s_base[1] = (t_lj >> 16) ? atomicAdd(&C->njobs[level + 1], (int)(t_lj >> 16)) : 0;
+      s_base[2] = t_tile ? atomicAdd(&C->ntiles[level + 1], (int)t_tile) : 0;
+      s_base[3] = t_pure ? atomicAdd(&C->npure, (int)t_pure) : 0;
+    }
+    __syncthreads();
+    long long nlid = s_base[0] + (o_lj & 0xffffu);
+    long long njid = s_base[1] + (o_lj >> 16);
+    long long nt0 = s_base[2] + o_tile;
+    long long np0 = s_base[3] + o_pure;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int d = tid * 4 + q;
@@ -581,21 +640,22 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
       const int cls = s_cls[d];
       if (cls == 3 && J.shift > 0) {
         const long long size = sz[q];
-        if (level + 1 > maxlevel) {
+        if (!deeper) {
           set_error(C, TTV_E_DEVICE);
           continue;
         }
-        const int jid = atomicAdd(&C->njobs[level + 1], 1);
+        const long long jid = njid++;
+        int nt = (int)((size + Tnext - 1) / Tnext);
+        const long long t0 = nt0;
+        nt0 += nt;
         if (jid >= W.L.jcap) {
           set_error(C, TTV_E_DEVICE);
           continue;
         }
-        int nt = (int)((size + Tnext - 1) / Tnext);
-        const int t0 = atomicAdd(&C->ntiles[level + 1], nt);
         Job N;
         N.start = gstart;
         N.size = size;
-        if ((long long)t0 + nt > W.L.tcap) {  // keep a valid, empty job in the slot
+        if (t0 + nt > W.L.tcap) {  // keep a valid, empty job in the slot
           set_error(C, TTV_E_DEVICE);
           nt = 0;
           N.size = 0;
@@ -610,9 +670,10 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
         N.pad = 0;
         W.jobs(level + 1)[jid] = N;
         int* T = W.tiles(level + 1);
-        for (int k = 0; k < nt; ++k) T[t0 + k] = jid;
+        for (int k = 0; k < nt; ++k) T[t0 + k] = (int)jid;
         continue;
       }
+      const long long lid = nlid++;
       Leaf Lf;
       Lf.start = gstart;
       Lf.base = dbase;
@@ -627,8 +688,9 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
         Lf.kind = kLeafPure;
         Lf.bits = 0;
         const int np = (int)((Lf.size + kPureTile - 1) / kPureTile);
-        const int p0 = atomicAdd(&C->npure, np);
-        if ((long long)p0 + np > W.L.pcap) {
+        const long long p0 = np0;
+        np0 += np;
+        if (p0 + np > W.L.pcap) {
           set_error(C, TTV_E_DEVICE);
           continue;
         }
@@ -642,7 +704,6 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
         Lf.size = (long long)s_start[nb] - s_start[d];
         Lf.bits = J.shift + bitlen64((unsigned long long)(nb - d - 1));
       }
-      const int lid = atomicAdd(&C->nleaves, 1);
       if (lid >= W.L.lcap) {
         set_error(C, TTV_E_DEVICE);
         continue;
@@ -650,7 +711,7 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
       W.leaves()[lid] = Lf;
       if (Lf.kind == kLeafPure) {
         int* pl = W.ptile_leaf();
-        for (int k = 0; k < Lf.nptiles; ++k) pl[Lf.ptile0 + k] = lid;
+        for (int k = 0; k < Lf.nptiles; ++k) pl[Lf.ptile0 + k] = (int)lid;
       }
       atomicOr(&W.bitmap()[gstart >> 5], 1u << (gstart & 31));
     }
@@ -663,14 +724,14 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
 // records keep their order (rounds of 2048; inside a round wave-major, then
 // item, then lane), so bucket contents are in input order.
 // ---------------------------------------------------------------------------
-template <typename IdxT, int F, int PM>
+template <typename IdxT, int F, int PM, int MO>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level, int T) {
   constexpr int IPT = kScatterIPT;
   constexpr int RW = 64 * IPT;            // records per wave per round
   constexpr int RN = kScatterThreads * IPT;
   __shared__ unsigned cursor[kNDig];
   __shared__ unsigned wcnt32[4][kNDig / 2];  // per-wave u16 counters, two per word
-  __shared__ RawSrc<IdxT, F> rsrc;
+  __shared__ IdxT stage[kScatterThreads / 64][64 * MO];
   auto wcnt = [&](int q, unsigned d) -> unsigned { return (wcnt32[q][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
@@ -702,10 +763,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
                                        : to_global((const u64x2*)W.rec(J.src)) + J.start + b;
     const TDesc* Dp = W.desc() + J.tensor;
     const long long roff = J.start - Dp->base + b;
-    if (J.src == kSrcRaw) {
-      if (threadIdx.x == 0) rsrc.set(*Dp);
-      __syncthreads();
-    }
+    RawSrc<IdxT, F, MO> S;
+    S.set(*Dp);
     gptr<u64x2> gdst = to_global((u64x2*)dst);
     for (long long rb = 0; rb < n; rb += RN) {
       uint64_t key[IPT], pay[IPT];
@@ -725,7 +784,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
             }
           }
         } else {
-          load_round<IdxT, F, PM, IPT>(rsrc, roff + i0, n - i0, C, key, pay);
+          const long long s0 = rb + (long long)w * RW;
+          load_round<IdxT, F, PM, IPT, MO>(S, roff + s0, n - s0, stage[w], C, key, pay);
         }
       }
 #pragma unroll
@@ -1048,6 +1108,28 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       if (j < nj) k[j] = (unsigned)(R[i < n ? i : n - 1].key - Lf.base);
     }
     TTV_PHASE(1)
+    // Distinct keys counted before the sort when the relative keys are narrow
+    // enough for a presence bitmap in the counter space: the aggregate is
+    // published this early, so the look-backs of later leaves rarely wait.
+    constexpr int kEarlyBits = 5 + MAXD + (NW >= 8 ? 3 : (NW >= 4 ? 2 : (NW >= 2 ? 1 : 0)));  // bits in cnt
+    static_assert((NW & (NW - 1)) == 0 && NW <= 8, "counter space is NW << MAXD words");
+    const bool early = !wide && Lf.bits <= kEarlyBits;
+    unsigned u_early = 0;
+    if (early) {
+      const int words = 1 << (Lf.bits > 5 ? Lf.bits - 5 : 0);
+      for (int q = tid; q < words; q += NT) cnt[q] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int i = w * 64 * nj + j * 64 + (int)ln;
+        if (j < nj && i < n) atomicOr(&cnt[k[j] >> 5], 1u << (k[j] & 31u));
+      }
+      __syncthreads();
+      unsigned c = 0;
+      for (int q = tid; q < words; q += NT) c += (unsigned)__popc(cnt[q]);
+      block_excl_scan<NT>(c, wsum, u_early);  // its barriers also end the bitmap's use
+      if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u_early);
+    }
     const int npass = (Lf.bits + MAXD - 1) / MAXD;
     const int dw = npass ? (Lf.bits + npass - 1) / npass : 0;
     const int nb = 1 << dw;
@@ -1155,7 +1237,11 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       hbw += (q < w) ? c : 0u;
       u += c;
     }
-    if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);
+    if (early) {
+      if (tid == 0 && u != u_early) set_error(C, TTV_E_DEVICE);  // the two counts agree by construction
+    } else if (tid == 0) {
+      publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);
+    }
     // wave 0 resolves this leaf's output offset while the others gather payloads
     if (w == 0) {
       const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
@@ -1253,7 +1339,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
 // ---------------------------------------------------------------------------
 // host launcher
 // ---------------------------------------------------------------------------
-template <typename IdxT, int F, int PM>
+template <typename IdxT, int F, int PM, int MO>
 static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   WsView W;
@@ -1268,13 +1354,13 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     const int gt = l == 1 ? (int)std::max<long long>(1, std::min<long long>(P.tiles1, 8LL * cus)) : 4 * cus;
     const int gj = l == 1 ? std::max(1, P.count) : 2 * cus;
     if (l == 1) prof_begin(TTV_PROF_HIST1, s);
-    hipLaunchKernelGGL(k_hist<IdxT>, dim3(gt), dim3(256), 0, s, W, l, T);
+    hipLaunchKernelGGL((k_hist<IdxT, MO>), dim3(gt), dim3(kHistThreads), 0, s, W, l, T);
     if (l == 1) prof_end(TTV_PROF_HIST1, s);
     hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 4 * cus), dim3(1024),
                        0, s, W, l);
     hipLaunchKernelGGL(k_classify, dim3(std::min(gj, 4 * cus)), dim3(1024), 0, s, W, l, Tn, P.levels);
     if (l == 1) prof_begin(TTV_PROF_SCATTER1, s);
-    hipLaunchKernelGGL((k_scatter<IdxT, F, PM>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
+    hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_pure<F>, dim3(2 * cus), dim3(256), 0, s, W);
@@ -1292,18 +1378,40 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
   return TTV_OK;
 }
 
+// Register/LDS class of the raw-index loaders: the widest row (stride_e of a
+// row-major tensor, else the order) over the tensors of the run.
+static int row_class(const PipePlan& P) {
+  int need = 1;
+  auto one = [&](const TDesc& D) {
+    const bool rowmajor = (D.order == 1 || D.stride_j == 1) && D.stride_e >= D.order && D.stride_e <= kMaxOrder;
+    need = std::max(need, rowmajor ? (int)D.stride_e : D.order);
+  };
+  if (P.descs.empty())
+    one(P.d0);
+  else
+    for (const TDesc& D : P.descs) one(D);
+  return need <= 3 ? 3 : (need <= 5 ? 5 : kMaxOrder);
+}
+
+template <typename IdxT, int F, int PM>
+static int launch_mo(const PipePlan& P, void* ws, hipStream_t s) {
+  switch (row_class(P)) {
+    case 3: return launch_impl<IdxT, F, PM, 3>(P, ws, s);
+    case 5: return launch_impl<IdxT, F, PM, 5>(P, ws, s);
+    default: return launch_impl<IdxT, F, PM, kMaxOrder>(P, ws, s);
+  }
+}
+
 int launch_pipeline(const PipePlan& P, void* ws, hipStream_t s) {
   const bool i64 = P.idx64 != 0;
   if (P.pipe_mode == kPipeSegMap) {
     if (P.form == kF64)
-      return i64 ? launch_impl<long long, kF64, kPipeSegMap>(P, ws, s)
-                 : launch_impl<int, kF64, kPipeSegMap>(P, ws, s);
-    return i64 ? launch_impl<long long, kC32, kPipeSegMap>(P, ws, s)
-               : launch_impl<int, kC32, kPipeSegMap>(P, ws, s);
+      return i64 ? launch_mo<long long, kF64, kPipeSegMap>(P, ws, s) : launch_mo<int, kF64, kPipeSegMap>(P, ws, s);
+    return i64 ? launch_mo<long long, kC32, kPipeSegMap>(P, ws, s) : launch_mo<int, kC32, kPipeSegMap>(P, ws, s);
   }
   if (P.form == kF64)
-    return i64 ? launch_impl<long long, kF64, kPipeTTV>(P, ws, s) : launch_impl<int, kF64, kPipeTTV>(P, ws, s);
-  return i64 ? launch_impl<long long, kC32, kPipeTTV>(P, ws, s) : launch_impl<int, kC32, kPipeTTV>(P, ws, s);
+    return i64 ? launch_mo<long long, kF64, kPipeTTV>(P, ws, s) : launch_mo<int, kF64, kPipeTTV>(P, ws, s);
+  return i64 ? launch_mo<long long, kC32, kPipeTTV>(P, ws, s) : launch_mo<int, kC32, kPipeTTV>(P, ws, s);
 }
 
 }  // namespace ttv
