@@ -940,7 +940,12 @@ __device__ __forceinline__ void publish(unsigned long long* S, int r, unsigned l
 
 // Decoupled look-back by one wave: 64 predecessors per step; the nearest
 // inclusive prefix ends the walk, the aggregates after it are added.
-__device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit, Ctrl* C) {
+// `early` is this lane's status word of the first window (predecessor
+// r-1-lane) read some time before, or 0: published words never change
+// meaning (an aggregate stays the leaf's count), so only the words still 0
+// are read again.
+__device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit, Ctrl* C,
+                                   unsigned long long early = 0) {
   const unsigned ln = lane_id();
   long long prefix = 0;
   for (int base = r - 1;; base -= 64) {
@@ -948,7 +953,9 @@ __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit,
     unsigned long long s = kFlagInc;  // before the first leaf: an inclusive prefix of 0
     if (j >= 0) {
       int spins = 0;
+      s = base == r - 1 ? early : 0ull;
       for (;;) {
+        if (s >> 62) break;
         s = __hip_atomic_load(&S[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (s >> 62) break;
         if (++spins > spin_limit) {
@@ -1032,6 +1039,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
   constexpr int MAXD = 9;  // widest LDS digit
   __shared__ unsigned sk[kCap];
   __shared__ unsigned short si[kCap];
+  __shared__ uint64_t spay[kCap];  // payloads in leaf order (no second read of the records)
   __shared__ unsigned cnt[NW << MAXD];
   __shared__ unsigned wsum[NW];
   __shared__ Seg<F> wagg[NW];
@@ -1061,6 +1069,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     __syncthreads();
     const OutInfo<IdxT, F>& O = sO;
     const gptr<const Rec> R = to_global(static_cast<const Rec*>(W.rec(Lf.src))) + Lf.start;
+    const gptr<const u64x2> Rv = to_global(reinterpret_cast<const u64x2*>(W.rec(Lf.src))) + Lf.start;
     const int n = (int)(Lf.size < (long long)kCap ? Lf.size : (long long)kCap);
     if (Lf.kind != kLeafPure && (Lf.size > kCap || Lf.size <= 0)) {  // excluded by classification
       if (tid == 0) {
@@ -1105,7 +1114,11 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       const int i = w * 64 * nj + j * 64 + (int)ln;
       ix[j] = (unsigned)i;
       k[j] = 0;
-      if (j < nj) k[j] = (unsigned)(R[i < n ? i : n - 1].key - Lf.base);
+      if (j < nj) {
+        const u64x2 rc = Rv[i < n ? i : n - 1];  // whole records: one coalesced 16-byte read per item
+        k[j] = (unsigned)(rc.x - Lf.base);
+        if (i < n) spay[i] = rc.y;
+      }
     }
     TTV_PHASE(1)
     // Distinct keys counted before the sort when the relative keys are narrow
@@ -1115,6 +1128,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     static_assert((NW & (NW - 1)) == 0 && NW <= 8, "counter space is NW << MAXD words");
     const bool early = !wide && Lf.bits <= kEarlyBits;
     unsigned u_early = 0;
+    unsigned long long lb_early = 0;
     if (early) {
       const int words = 1 << (Lf.bits > 5 ? Lf.bits - 5 : 0);
       for (int q = tid; q < words; q += NT) cnt[q] = 0u;
@@ -1129,6 +1143,11 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       for (int q = tid; q < words; q += NT) c += (unsigned)__popc(cnt[q]);
       block_excl_scan<NT>(c, wsum, u_early);  // its barriers also end the bitmap's use
       if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u_early);
+      // the look-back's first window is read now and used after the sort
+      if (w == 0 && !first) {
+        const int jp = r - 1 - (int)ln;
+        lb_early = jp >= 0 ? __hip_atomic_load(&S[jp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagInc;
+      }
     }
     const int npass = (Lf.bits + MAXD - 1) / MAXD;
     const int dw = npass ? (Lf.bits + npass - 1) / npass : 0;
@@ -1244,7 +1263,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     }
     // wave 0 resolves this leaf's output offset while the others gather payloads
     if (w == 0) {
-      const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
+      const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early);
       if (ln == 0) {
         if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u));
         s_prefix = prefix;
@@ -1260,7 +1279,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       for (int j = 0; j < IPT; ++j) {
         const int p = pw + j * 64 + (int)ln;
         pay[j] = 0;
-        if (j < nj) pay[j] = R[si[p < n ? p : n - 1]].pay;
+        if (j < nj) pay[j] = spay[si[p < n ? p : n - 1]];
       }
       Acc c = FO::zero();  // value of the segment open at the end of the previous round
 #pragma unroll
@@ -1314,7 +1333,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       if (p < n) {
         const long long rowi = prefix + hrun + upto - 1;
         if (PM == kPipeSegMap) {
-          seg_out[(long long)R[si[p]].pay] = (int32_t)rowi;
+          seg_out[(long long)spay[si[p]]] = (int32_t)rowi;
         } else {
           bool end;
           if (p == n - 1)
