@@ -89,6 +89,7 @@ extern "C" int ttv_debug_phases_reset() {
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagInc = 2ull << 62;
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
+constexpr int kClassifySlices = 16;           // blocks per level-1 job in classify
 constexpr int kBitmapWordsPerBlock = 8192;  // 256 threads x 32 words
 
 // ---------------------------------------------------------------------------
@@ -503,7 +504,10 @@ __device__ __forceinline__ int block_excl_mm(int v, int ident, int* wsum) {
 // ---------------------------------------------------------------------------
 // classify: per job, bucket starts and the fate of every bucket.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnext, int maxlevel) {
+// A job's 2^r digits are emitted by `slices` blocks (digit ranges); each of
+// them recomputes the job-wide scans from the digit totals, which stay in
+// place (the scatter derives the bucket starts itself).
+__global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnext, int maxlevel, int slices) {
   __shared__ unsigned s_start[kNDig + 1];
   __shared__ int s_nb[kNDig];
   __shared__ unsigned char s_cls[kNDig];  // 0 empty, 1 small, 2 medium, 3 large
@@ -513,11 +517,14 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
   if (aborted(C)) return;
   const int njobs = clampi(C->njobs[level], W.L.jcap);
   const int tid = threadIdx.x;
-  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+  for (long long it = blockIdx.x; it < (long long)njobs * slices; it += gridDim.x) {
+    const int j = (int)(it / slices);
+    const int slice = (int)(it % slices);
     const Job J = W.jobs(level)[j];
     if (J.size == 0) continue;  // uniform over the block
     const int nd = 1 << J.r;
-    unsigned* tot = W.starts() + (size_t)j * kNDig;
+    const int dlo = (int)((long long)nd * slice / slices), dhi = (int)((long long)nd * (slice + 1) / slices);
+    const unsigned* tot = W.starts() + (size_t)j * kNDig;
     unsigned sz[4];
     unsigned s = 0;
 #pragma unroll
@@ -533,7 +540,6 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
       const int d = tid * 4 + q;
       if (d < nd) {
         s_start[d] = ex;
-        tot[d] = ex;
         s_cls[d] = sz[q] == 0 ? 0 : (sz[q] <= (unsigned)kSmall ? 1 : (sz[q] <= (unsigned)kCap ? 2 : 3));
       }
       ex += sz[q];
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int d = tid * 4 + q;
-      if (d >= nd || !bnd[q]) continue;
+      if (d < dlo || d >= dhi || !bnd[q]) continue;
       if (s_cls[d] == 3 && J.shift > 0) {
         if (deeper) {
           c_lj += 1u << 16;
@@ -634,7 +640,7 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int d = tid * 4 + q;
-      if (d >= nd || !bnd[q]) continue;
+      if (d < dlo || d >= dhi || !bnd[q]) continue;
       const long long gstart = J.start + s_start[d];
       const unsigned long long dbase = J.prefix | ((unsigned long long)d << J.shift);
       const int cls = s_cls[d];
@@ -732,6 +738,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
   __shared__ unsigned cursor[kNDig];
   __shared__ unsigned wcnt32[4][kNDig / 2];  // per-wave u16 counters, two per word
   __shared__ IdxT stage[kScatterThreads / 64][64 * MO];
+  __shared__ unsigned wsum_s[kScatterThreads / 64];
   auto wcnt = [&](int q, unsigned d) -> unsigned { return (wcnt32[q][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
@@ -746,8 +753,24 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
     const int nd = 1 << J.r;
     const unsigned mask = (unsigned)nd - 1u;
     const unsigned* row = W.table() + (size_t)t * kNDig;
-    const unsigned* st = W.starts() + (size_t)jid * kNDig;
-    for (int i = threadIdx.x; i < nd; i += kScatterThreads) cursor[i] = st[i] + row[i];
+    const unsigned* tot = W.starts() + (size_t)jid * kNDig;
+    {  // bucket starts: exclusive scan of the job's digit totals, plus this tile's offsets
+      constexpr int DPT = kNDig / kScatterThreads;
+      const int d0 = threadIdx.x * DPT;
+      unsigned v[DPT], sum = 0;
+#pragma unroll
+      for (int q = 0; q < DPT; ++q) {
+        v[q] = d0 + q < nd ? tot[d0 + q] : 0u;
+        sum += v[q];
+      }
+      unsigned all;
+      unsigned ex = block_excl_scan<kScatterThreads>(sum, wsum_s, all);
+#pragma unroll
+      for (int q = 0; q < DPT; ++q) {
+        if (d0 + q < nd) cursor[d0 + q] = ex + row[d0 + q];
+        ex += v[q];
+      }
+    }
     for (int i = threadIdx.x; i < kNDig / 2; i += kScatterThreads) {
       wcnt32[0][i] = 0;
       wcnt32[1][i] = 0;
@@ -1377,7 +1400,9 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     if (l == 1) prof_end(TTV_PROF_HIST1, s);
     hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 4 * cus), dim3(1024),
                        0, s, W, l);
-    hipLaunchKernelGGL(k_classify, dim3(std::min(gj, 4 * cus)), dim3(1024), 0, s, W, l, Tn, P.levels);
+    const int slices = l == 1 ? kClassifySlices : 1;
+    hipLaunchKernelGGL(k_classify, dim3(std::min(gj * slices, 4 * cus)), dim3(1024), 0, s, W, l, Tn, P.levels,
+                       slices);
     if (l == 1) prof_begin(TTV_PROF_SCATTER1, s);
     hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
