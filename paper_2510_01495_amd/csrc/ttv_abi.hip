@@ -169,7 +169,7 @@ Layout make_layout(long long total, int count, int levels, int T1, int T2, long 
   L.lcap = (long long)levels * (3 * ((total + kSmall - 1) / kSmall) + L.jcap) + count + 64;
   L.pcap = total / kPureTile + total / kCap + count + 2;
   L.words = (total + 31) / 32 + 1;
-  L.wblocks = (L.words + 8191) / 8192;
+  L.wblocks = (L.words + kBitmapWordsPerBlock - 1) / kBitmapWordsPerBlock;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;

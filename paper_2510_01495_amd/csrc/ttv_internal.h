@@ -25,6 +25,7 @@ constexpr int kMaxLevels = 8;            // 64-bit keys with 12-bit digits need 
 constexpr int kPureTile = 16384;         // records per block when reducing a single-key bucket
 constexpr int kScatterThreads = 256;     // 4 waves
 constexpr int kHistThreads = 1024;       // 16 waves
+constexpr int kBitmapWordsPerBlock = 2048;  // leaf-start bitmap words per block: 256 threads x 8
 constexpr int kHistIPT = 4;
 constexpr int kScatterIPT = 8;           // records per thread per round
 constexpr int kFinishThreads = 512;     // 8 waves
@@ -124,6 +125,8 @@ struct Ctrl {
   int32_t ticket;
   int32_t error;          // first device-side error (TTV_E_* code), 0 if none
   long long total;        // records over all tensors
+  int32_t bm_done;        // bitmap blocks finished (the last one scans the block sums)
+  int32_t pad;
 };
 
 // Byte offsets of every region inside the caller's workspace.

@@ -90,7 +90,6 @@ constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagInc = 2ull << 62;
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
 constexpr int kClassifySlices = 16;           // blocks per level-1 job in classify
-constexpr int kBitmapWordsPerBlock = 8192;  // 256 threads x 32 words
 
 // ---------------------------------------------------------------------------
 // Records from the COO input: key = remaining-mode indices packed with the
@@ -310,6 +309,7 @@ __global__ __launch_bounds__(256) void k_init(WsView W, TDesc d0, const TDesc* d
     C->nleaves = 0;
     C->npure = 0;
     C->ticket = 0;
+    C->bm_done = 0;
     C->error = 0;
     long long tile = 0, total = 0;
     int nj = 0;
@@ -865,8 +865,58 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
 // ---------------------------------------------------------------------------
 // pure reduce: partial sums of single-key leaves, kPureTile records per block
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// leaf numbering: popcount prefix of the leaf-start bitmap.  Every block
+// prefixes its words; the block that finishes last scans the block sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bitmap(WsView W) {
+  constexpr int WPT = kBitmapWordsPerBlock / 256;
+  __shared__ unsigned wsum[4];
+  __shared__ int s_last;
+  Ctrl* C = W.ctrl();
+  const long long w0 = (long long)blockIdx.x * kBitmapWordsPerBlock + threadIdx.x * WPT;
+  const gptr<const unsigned> bm = to_global((const unsigned*)W.bitmap());
+  unsigned c[WPT];
+  unsigned s = 0;
+#pragma unroll
+  for (int q = 0; q < WPT; ++q) {
+    const long long wi = w0 + q;
+    c[q] = wi < W.L.words ? (unsigned)__popc(bm[wi]) : 0u;
+    s += c[q];
+  }
+  unsigned tot;
+  unsigned ex = block_excl_scan<256>(s, wsum, tot);
+  unsigned* wp = W.wordpre();
+#pragma unroll
+  for (int q = 0; q < WPT; ++q) {
+    const long long wi = w0 + q;
+    if (wi < W.L.words) wp[wi] = ex;
+    ex += c[q];
+  }
+  unsigned* bp = W.blockpre();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&bp[blockIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int done = __hip_atomic_fetch_add(&C->bm_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = done == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  const long long n = W.L.wblocks;
+  unsigned carry = 0;
+  for (long long b0 = 0; b0 < n; b0 += 256) {
+    const long long i = b0 + threadIdx.x;
+    const unsigned v = i < n ? __hip_atomic_load(&bp[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    unsigned t;
+    const unsigned e = block_excl_scan<256>(v, wsum, t);
+    if (i < n) bp[i] = carry + e;
+    carry += t;
+  }
+}
+
+// Pure leaves: partial sums of kPureTile records each (combined in FP64 by
+// the finishing pass); then every leaf is placed at its rank (key order).
 template <int F>
-__global__ __launch_bounds__(256) void k_pure(WsView W) {
+__global__ __launch_bounds__(256) void k_leaves(WsView W) {
   using FO = FormOps<F>;
   using Acc = typename FO::Acc;
   __shared__ Acc red[256];
@@ -889,53 +939,6 @@ __global__ __launch_bounds__(256) void k_pure(WsView W) {
     if (threadIdx.x == 0) W.partials()[p] = FO::to_f64(red[0]);
     __syncthreads();
   }
-}
-
-// ---------------------------------------------------------------------------
-// leaf numbering: popcount prefix of the leaf-start bitmap
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bm_a(WsView W) {
-  __shared__ unsigned wsum[4];
-  const long long w0 = (long long)blockIdx.x * kBitmapWordsPerBlock + threadIdx.x * 32;
-  const unsigned* bm = W.bitmap();
-  unsigned c[32];
-  unsigned s = 0;
-#pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    const long long wi = w0 + q;
-    c[q] = wi < W.L.words ? (unsigned)__popc(bm[wi]) : 0u;
-    s += c[q];
-  }
-  unsigned tot;
-  unsigned ex = block_excl_scan<256>(s, wsum, tot);
-  unsigned* wp = W.wordpre();
-#pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    const long long wi = w0 + q;
-    if (wi < W.L.words) wp[wi] = ex;
-    ex += c[q];
-  }
-  if (threadIdx.x == 0) W.blockpre()[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(1024) void k_bm_b(WsView W) {
-  __shared__ unsigned wsum[16];
-  unsigned* bp = W.blockpre();
-  const long long n = W.L.wblocks;
-  unsigned carry = 0;
-  for (long long b0 = 0; b0 < n; b0 += 1024) {
-    const long long i = b0 + threadIdx.x;
-    const unsigned v = i < n ? bp[i] : 0u;
-    unsigned tot;
-    const unsigned ex = block_excl_scan<1024>(v, wsum, tot);
-    if (i < n) bp[i] = carry + ex;
-    carry += tot;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_rank(WsView W) {
-  Ctrl* C = W.ctrl();
-  if (aborted(C)) return;
   const int nl = clampi(C->nleaves, W.L.lcap);
   const Leaf* Ls = W.leaves();
   Leaf* O = W.ordered();
@@ -1407,10 +1410,8 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
-  hipLaunchKernelGGL(k_pure<F>, dim3(2 * cus), dim3(256), 0, s, W);
-  hipLaunchKernelGGL(k_bm_a, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
-  hipLaunchKernelGGL(k_bm_b, dim3(1), dim3(1024), 0, s, W);
-  hipLaunchKernelGGL(k_rank, dim3(2 * cus), dim3(256), 0, s, W);
+  hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
+  hipLaunchKernelGGL(k_leaves<F>, dim3(2 * cus), dim3(256), 0, s, W);
   prof_begin(TTV_PROF_FINISH, s);
   hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(2 * cus), dim3(kFinishThreads), 0, s, W, P.spin_limit);
   prof_end(TTV_PROF_FINISH, s);
