@@ -96,9 +96,9 @@ constexpr int kClassifySlices = 16;           // blocks per level-1 job in class
 // first remaining mode most significant; payload = value times the vector
 // entries of the contracted modes (ascending), or the nonzero's index.
 // ---------------------------------------------------------------------------
-// What a tile needs to read nonzeros of one tensor, copied once per tile
-// from the (wave-uniform) descriptor into registers: fields left in memory
-// would be loaded again after every barrier or fence of the round loop.
+// What a tile needs to read nonzeros of one tensor, staged in LDS once per
+// tile (descriptor fields read from global memory would be fetched again
+// after every store).
 template <typename IdxT, int F, int MO>
 struct RawSrc {
   using In = typename FormOps<F>::In;
@@ -373,6 +373,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(WsView W, int level, int 
   constexpr int IPT = MO <= 3 ? kHistIPT : (MO <= 5 ? 3 : 2);  // rows per lane per round within 128 VGPRs
   __shared__ unsigned hist[kNDig];
   __shared__ IdxT stage[NT / 64][64 * MO];
+  __shared__ RawSrc<IdxT, kF64, MO> rsrc;
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int ntiles = clampi(C->ntiles[level], W.L.tcap);
@@ -387,9 +388,9 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(WsView W, int level, int 
     const unsigned mask = (unsigned)nd - 1u;
     for (int i = threadIdx.x; i < nd; i += NT) hist[i] = 0u;
     const TDesc* Dp = W.desc() + J.tensor;
-    RawSrc<IdxT, kF64, MO> S;
-    S.set(*Dp);
+    if (threadIdx.x == 0 && J.src == kSrcRaw) rsrc.set(*Dp);
     __syncthreads();
+    const RawSrc<IdxT, kF64, MO>& S = rsrc;
     const long long b = (long long)(t - J.tile0) * T;
     const long long n = (J.size - b < (long long)T) ? J.size - b : (long long)T;
     const long long roff = J.start - Dp->base + b;
@@ -504,101 +505,99 @@ __device__ __forceinline__ int block_excl_mm(int v, int ident, int* wsum) {
 // ---------------------------------------------------------------------------
 // classify: per job, bucket starts and the fate of every bucket.
 // ---------------------------------------------------------------------------
-// A job's 2^r digits are emitted by `slices` blocks (digit ranges); each of
-// them recomputes the job-wide scans from the digit totals, which stay in
-// place (the scatter derives the bucket starts itself).
-__global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnext, int maxlevel, int slices) {
-  __shared__ unsigned s_start[kNDig + 1];
-  __shared__ int s_nb[kNDig];
-  __shared__ unsigned char s_cls[kNDig];  // 0 empty, 1 small, 2 medium, 3 large
-  __shared__ unsigned wsum[16];
-  __shared__ int wsi[16];
-  Ctrl* C = W.ctrl();
-  if (aborted(C)) return;
-  const int njobs = clampi(C->njobs[level], W.L.jcap);
+// Shared memory of one classify item.
+struct ClassifySmem {
+  unsigned s_start[kNDig + 1];
+  int s_bd[kNDig];             // the digit itself if it starts a bucket group, else nd
+  int s_nb[kNDig];             // first group start after the digit
+  unsigned char s_cls[kNDig];  // 0 empty, 1 small, 2 medium, 3 large
+  unsigned wsum[16];
+  int wsi[16];
+};
+
+// One classify item: digits [dlo, dhi) of job j at this level (a job's 2^r
+// digits are split over `slices` items; each recomputes the job-wide scans
+// from the digit totals, which stay in place -- the scatter derives the
+// bucket starts itself).  NT threads, kNDig/NT digits per thread.
+template <int NT>
+__device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int Tnext, int maxlevel, int j, int slice, int slices,
+                              ClassifySmem& sm) {
+  constexpr int DPT = kNDig / NT;
+  unsigned* s_start = sm.s_start;
+  int* s_bd = sm.s_bd;
+  int* s_nb = sm.s_nb;
+  unsigned char* s_cls = sm.s_cls;
+  unsigned* wsum = sm.wsum;
+  int* wsi = sm.wsi;
   const int tid = threadIdx.x;
-  for (long long it = blockIdx.x; it < (long long)njobs * slices; it += gridDim.x) {
-    const int j = (int)(it / slices);
-    const int slice = (int)(it % slices);
+  {
     const Job J = W.jobs(level)[j];
-    if (J.size == 0) continue;  // uniform over the block
+    if (J.size == 0) return;  // uniform over the block
     const int nd = 1 << J.r;
     const int dlo = (int)((long long)nd * slice / slices), dhi = (int)((long long)nd * (slice + 1) / slices);
     const unsigned* tot = W.starts() + (size_t)j * kNDig;
-    unsigned sz[4];
+    // per-thread digit runs are kept in LDS, not in (dynamically indexed) arrays
     unsigned s = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
-      sz[q] = d < nd ? tot[d] : 0u;
-      s += sz[q];
+#pragma unroll 4
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
+      const unsigned v = d < nd ? tot[d] : 0u;
+      if (d < nd) s_start[d] = v;
+      s += v;
     }
     unsigned total;
-    unsigned ex = block_excl_scan<1024>(s, wsum, total);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
+    unsigned ex = block_excl_scan<NT>(s, wsum, total);
+#pragma unroll 4
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
       if (d < nd) {
+        const unsigned v = s_start[d];
         s_start[d] = ex;
-        s_cls[d] = sz[q] == 0 ? 0 : (sz[q] <= (unsigned)kSmall ? 1 : (sz[q] <= (unsigned)kCap ? 2 : 3));
+        s_cls[d] = v == 0 ? 0 : (v <= (unsigned)kSmall ? 1 : (v <= (unsigned)kCap ? 2 : 3));
+        ex += v;
       }
-      ex += sz[q];
     }
     if (tid == 0) s_start[nd] = total;
     __syncthreads();
     // previous non-empty digit (exclusive max-scan)
     int lm = -1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
       if (d < nd && s_cls[d] != 0) lm = d;
     }
     int prev = block_excl_mm<true>(lm, -1, wsi);
-    // chunk heads and boundaries
-    bool bnd[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
-      bnd[q] = false;
-      if (d < nd && s_cls[d] != 0) {
+    // bucket-group starts: every non-small bucket, and a small bucket after a
+    // non-small one or in a new kSmall window
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
+      if (d >= nd) break;
+      bool bnd = false;
+      if (s_cls[d] != 0) {
         if (s_cls[d] != 1) {
-          bnd[q] = true;
+          bnd = true;
         } else {
-          const bool head = prev < 0 || s_cls[prev] != 1 ||
-                            (J.start + s_start[prev]) / kSmall != (J.start + s_start[d]) / kSmall;
-          bnd[q] = head;
+          bnd = prev < 0 || s_cls[prev] != 1 ||
+                (J.start + s_start[prev]) / kSmall != (J.start + s_start[d]) / kSmall;
         }
         prev = d;
       }
-    }
-    // next boundary after each digit (suffix min-scan, done on reversed order)
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
-      if (d < nd) s_nb[d] = bnd[q] ? d : nd;
+      s_bd[d] = bnd ? d : nd;
     }
     __syncthreads();
-    const int rt = 1023 - tid;  // this thread scans the digits of thread rt, reversed
+    // next group start after each digit (suffix min-scan, done on reversed order)
+    const int rt = NT - 1 - tid;  // this thread scans the digits of thread rt, reversed
     int rv = nd;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = rt * 4 + q;
-      if (d < nd) rv = min(rv, s_nb[d]);
+    for (int q = 0; q < DPT; ++q) {
+      const int d = rt * DPT + q;
+      if (d < nd) rv = min(rv, s_bd[d]);
     }
     int nxt = block_excl_mm<false>(rv, nd, wsi);  // min over digits of threads > rt
-    int nbq[4];
-#pragma unroll
-    for (int q = 3; q >= 0; --q) {
-      const int d = rt * 4 + q;
-      nbq[q] = nxt;  // first boundary strictly after digit d
-      if (d < nd) nxt = min(nxt, s_nb[d]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = rt * 4 + q;
-      if (d < nd) s_nb[d] = nbq[q];
+    for (int q = DPT - 1; q >= 0; --q) {
+      const int d = rt * DPT + q;
+      if (d < nd) {
+        s_nb[d] = nxt;  // first group start strictly after digit d
+        nxt = min(nxt, s_bd[d]);
+      }
     }
     __syncthreads();
     // emit jobs and leaves; slots come from one block-wide reservation per
@@ -608,24 +607,25 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
     const bool deeper = J.shift > 0 && level + 1 <= maxlevel;
     unsigned c_lj = 0, c_tile = 0, c_pure = 0;  // c_lj: leaves (low 16 bits), jobs (high 16 bits)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
-      if (d < dlo || d >= dhi || !bnd[q]) continue;
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
+      if (d < dlo || d >= dhi || s_bd[d] != d) continue;
+      const unsigned szd = s_start[d + 1] - s_start[d];
       if (s_cls[d] == 3 && J.shift > 0) {
         if (deeper) {
           c_lj += 1u << 16;
-          c_tile += (unsigned)(((unsigned long long)sz[q] + Tnext - 1) / Tnext);
+          c_tile += (unsigned)(((unsigned long long)szd + Tnext - 1) / Tnext);
         }
       } else {
         c_lj += 1u;
-        if (s_cls[d] == 3) c_pure += (unsigned)(((unsigned long long)sz[q] + kPureTile - 1) / kPureTile);
+        if (s_cls[d] == 3) c_pure += (unsigned)(((unsigned long long)szd + kPureTile - 1) / kPureTile);
       }
     }
     __shared__ long long s_base[4];
     unsigned t_lj, t_tile, t_pure;
-    unsigned o_lj = block_excl_scan<1024>(c_lj, wsum, t_lj);
-    unsigned o_tile = block_excl_scan<1024>(c_tile, wsum, t_tile);
-    unsigned o_pure = block_excl_scan<1024>(c_pure, wsum, t_pure);
+    unsigned o_lj = block_excl_scan<NT>(c_lj, wsum, t_lj);
+    unsigned o_tile = block_excl_scan<NT>(c_tile, wsum, t_tile);
+    unsigned o_pure = block_excl_scan<NT>(c_pure, wsum, t_pure);
     if (tid == 0) {
       s_base[0] = (t_lj & 0xffffu) ? atomicAdd(&C->nleaves, (int)(t_lj & 0xffffu)) : 0;
       s_base[1] = (t_lj >> 16) ? atomicAdd(&C->njobs[level + 1], (int)(t_lj >> 16)) : 0;
@@ -638,14 +638,15 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
     long long nt0 = s_base[2] + o_tile;
     long long np0 = s_base[3] + o_pure;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = tid * 4 + q;
-      if (d < dlo || d >= dhi || !bnd[q]) continue;
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
+      if (d < dlo || d >= dhi || s_bd[d] != d) continue;
       const long long gstart = J.start + s_start[d];
       const unsigned long long dbase = J.prefix | ((unsigned long long)d << J.shift);
       const int cls = s_cls[d];
+      const unsigned szd = s_start[d + 1] - s_start[d];
       if (cls == 3 && J.shift > 0) {
-        const long long size = sz[q];
+        const long long size = szd;
         if (!deeper) {
           set_error(C, TTV_E_DEVICE);
           continue;
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
       Lf.pad = 0;
       Lf.kind = kLeafSort;
       if (cls == 3) {  // single key, too large for one block: pure leaf
-        Lf.size = sz[q];
+        Lf.size = szd;
         Lf.kind = kLeafPure;
         Lf.bits = 0;
         const int np = (int)((Lf.size + kPureTile - 1) / kPureTile);
@@ -703,7 +704,7 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
         Lf.ptile0 = p0;
         Lf.nptiles = np;
       } else if (cls == 2) {
-        Lf.size = sz[q];
+        Lf.size = szd;
         Lf.bits = J.shift;
       } else {
         const int nb = s_nb[d];
@@ -730,24 +731,54 @@ __global__ __launch_bounds__(1024) void k_classify(WsView W, int level, int Tnex
 // records keep their order (rounds of 2048; inside a round wave-major, then
 // item, then lane), so bucket contents are in input order.
 // ---------------------------------------------------------------------------
+template <typename IdxT, int MO>
+struct ScatterSmem {
+  unsigned cursor[kNDig];
+  unsigned wcnt32[4][kNDig / 2];  // per-wave u16 counters, two per word
+  IdxT stage[kScatterThreads / 64][64 * MO];
+  unsigned wsum[kScatterThreads / 64];
+};
+
+// The first `gc` blocks classify this level's buckets (classify_item over
+// njobs*slices items); the others scatter its tiles.  Neither role reads what
+// the other writes in this launch.
 template <typename IdxT, int F, int PM, int MO>
-__global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level, int T) {
+__global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level, int T, int Tnext, int maxlevel,
+                                                             int slices, int gc) {
   constexpr int IPT = kScatterIPT;
   constexpr int RW = 64 * IPT;            // records per wave per round
   constexpr int RN = kScatterThreads * IPT;
-  __shared__ unsigned cursor[kNDig];
-  __shared__ unsigned wcnt32[4][kNDig / 2];  // per-wave u16 counters, two per word
-  __shared__ IdxT stage[kScatterThreads / 64][64 * MO];
-  __shared__ unsigned wsum_s[kScatterThreads / 64];
-  auto wcnt = [&](int q, unsigned d) -> unsigned { return (wcnt32[q][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
+  union Smem {
+    ScatterSmem<IdxT, MO> sc;
+    ClassifySmem cl;
+  };
+  __shared__ Smem smem;  // the two roles share the block's LDS
+  __shared__ RawSrc<IdxT, F, MO> rsrc;
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
+  if ((int)blockIdx.x < gc) {
+    ClassifySmem& cs = smem.cl;
+    const int njobs = clampi(C->njobs[level], W.L.jcap);
+    for (long long it = blockIdx.x; it < (long long)njobs * slices; it += gc) {
+      classify_item<kScatterThreads>(W, C, level, Tnext, maxlevel, (int)(it / slices), (int)(it % slices), slices,
+                                     cs);
+      __syncthreads();
+    }
+    return;
+  }
+  ScatterSmem<IdxT, MO>& ss = smem.sc;
+  unsigned* cursor = ss.cursor;
+  auto& wcnt32 = ss.wcnt32;
+  auto& stage = ss.stage;
+  unsigned* wsum_s = ss.wsum;
+  auto wcnt = [&](int q, unsigned d) -> unsigned { return (wcnt32[q][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
   const int ntiles = clampi(C->ntiles[level], W.L.tcap);
   const Job* jobs = W.jobs(level);
   const int* tj = W.tiles(level);
   const int w = threadIdx.x >> 6;
   const unsigned ln = lane_id();
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int bid = (int)blockIdx.x - gc, nsb = (int)gridDim.x - gc;
+  for (int t = bid; t < ntiles; t += nsb) {
     const int jid = tj[t];
     const Job J = jobs[jid];
     const int nd = 1 << J.r;
@@ -771,6 +802,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
         ex += v[q];
       }
     }
+    if (threadIdx.x == 0 && J.src == kSrcRaw) rsrc.set(W.desc()[J.tensor]);
     for (int i = threadIdx.x; i < kNDig / 2; i += kScatterThreads) {
       wcnt32[0][i] = 0;
       wcnt32[1][i] = 0;
@@ -786,8 +818,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
                                        : to_global((const u64x2*)W.rec(J.src)) + J.start + b;
     const TDesc* Dp = W.desc() + J.tensor;
     const long long roff = J.start - Dp->base + b;
-    RawSrc<IdxT, F, MO> S;
-    S.set(*Dp);
+    const RawSrc<IdxT, F, MO>& S = rsrc;
     gptr<u64x2> gdst = to_global((u64x2*)dst);
     for (long long rb = 0; rb < n; rb += RN) {
       uint64_t key[IPT], pay[IPT];
@@ -1403,11 +1434,12 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     if (l == 1) prof_end(TTV_PROF_HIST1, s);
     hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 4 * cus), dim3(1024),
                        0, s, W, l);
+    // classify blocks first (short), then the scatter's tiles
     const int slices = l == 1 ? kClassifySlices : 1;
-    hipLaunchKernelGGL(k_classify, dim3(std::min(gj * slices, 4 * cus)), dim3(1024), 0, s, W, l, Tn, P.levels,
-                       slices);
+    const int gc = std::min(gj * slices, 4 * cus);
     if (l == 1) prof_begin(TTV_PROF_SCATTER1, s);
-    hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gt), dim3(kScatterThreads), 0, s, W, l, T);
+    hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gc + gt), dim3(kScatterThreads), 0, s, W, l, T, Tn,
+                       P.levels, slices, gc);
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
