@@ -45,18 +45,18 @@ def sha(path):
 
 
 def kernel_traffic(name, workload):
-    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
+    """HBM bytes per launch of kernel `name` from the committed rocprofv3 PMC
+    summary of `workload`, if it was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"pipeline_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
     try:
         with open(p) as f:
             t = json.load(f)
-        src = os.path.join(ROOT, "paper_2510_01495_amd", "csrc", t["source"])
-        if sha(src) != t["source_sha"]:
-            return None
-        return float(t["bytes_per_launch"])
+        for src, digest in t["source_sha"].items():
+            if sha(os.path.join(ROOT, "paper_2510_01495_amd", "csrc", src)) != digest:
+                return None
+        return float(t["kernels"][name]["bytes_per_launch"])
     except Exception:
         return None
 
@@ -192,20 +192,8 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # HIP events around every launch of the dominant kernel, on its stream
+    # the timed steps: K steps of the whole path, synchronised on both sides
     K = args.steps
-    nprof = 3 * K
-    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(nprof)]
-    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(nprof)]
-    for e in ev_s + ev_e:  # torch creates the HIP event on first record
-        e.record()
-    torch.cuda.synchronize()
-    from ctypes import c_void_p
-    cs = (c_void_p * nprof)(*[e.cuda_event for e in ev_s])
-    ce = (c_void_p * nprof)(*[e.cuda_event for e in ev_e])
-    lib = L.load()
-    L.check(lib.ttv_profile_events(L.PROF_FINISH, cs, ce, nprof), "ttv_profile_events")
-
     torch.cuda.synchronize()
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     w0 = time.perf_counter()
@@ -215,19 +203,47 @@ def main():
     s1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    nrec = lib.ttv_profile_count()
-    lib.ttv_profile_events(L.PROF_NONE, None, None, 0)
     ms_step = s0.elapsed_time(s1) / K
-    fin_ms = sum(ev_s[i].elapsed_time(ev_e[i]) for i in range(min(nrec, nprof))) / max(1, min(nrec, nprof))
 
     nnz = X.nnz
     nnz_out = [int(op.out_nnz.item()) for op in ops]
     value = 4 * nnz / (ms_step * 1e-3)
-    # algorithmic bytes of one finish launch: read every 16-byte record once,
-    # write every output row once ((d-1) int64 indices + one FP64 value)
-    fin_bytes = 16 * nnz + np.mean(nnz_out) * (2 * 8 + 8)
-    achieved = fin_bytes / (fin_ms * 1e-3) / 1e9
-    traffic = kernel_traffic("finish", "uniform1e7")
+
+    # per-kernel rooflines: HIP events around every launch of one kernel (on
+    # the stream it is launched on), over K more steps per kernel
+    lib = L.load()
+    from ctypes import c_void_p
+    nprof = 3 * K
+    # algorithmic bytes per launch (each TTV launch; the all-but-one product
+    # does not use these kernels):
+    #   hist, level 1: every index once (3 x int64 per nonzero)
+    #   scatter, level 1: indices + value once, one 16-byte record written
+    #   finish: every record read once, every output row written once
+    #           (2 x int64 indices + one FP64 value)
+    alg = {"k_scatter": 48 * nnz, "k_finish": 16 * nnz + float(np.mean(nnz_out)) * (2 * 8 + 8),
+           "k_hist": 24 * nnz}
+    which = {"k_scatter": L.PROF_SCATTER1, "k_finish": L.PROF_FINISH, "k_hist": L.PROF_HIST1}
+    kernels = {}
+    for name, kid in which.items():
+        ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(nprof)]
+        ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(nprof)]
+        for e in ev_s + ev_e:  # torch creates the HIP event on first record
+            e.record()
+        torch.cuda.synchronize()
+        cs = (c_void_p * nprof)(*[e.cuda_event for e in ev_s])
+        ce = (c_void_p * nprof)(*[e.cuda_event for e in ev_e])
+        L.check(lib.ttv_profile_events(kid, cs, ce, nprof), "ttv_profile_events")
+        for _ in range(K):
+            step()
+        torch.cuda.synchronize()
+        nrec = min(lib.ttv_profile_count(), nprof)
+        lib.ttv_profile_events(L.PROF_NONE, None, None, 0)
+        avg_ms = sum(ev_s[i].elapsed_time(ev_e[i]) for i in range(nrec)) / max(1, nrec)
+        achieved = alg[name] / (avg_ms * 1e-3) / 1e9
+        kernels[name] = {"avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": alg[name], "achieved": achieved,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": kernel_traffic(name, "uniform1e7"),
+                         "launches_timed": nrec}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_launch_us"])
 
     # correctness of what was timed: sampled rows against the oracle
     err = max(sampled_error(X, m, vecs[m], ops[m].out_subs[:nnz_out[m]], ops[m].out_vals[:nnz_out[m]], 100, m)
@@ -255,9 +271,11 @@ def main():
         "config": {"workload": "10^4 x 10^4 x 10^4 COO, 1e7 distinct uniform coordinates, int64 indices, "
                                "FP64 U[0,1) values; ttv in modes 0, 1, 2 + all-but-one keeping mode 0",
                    "nnz": nnz, "nnz_out": nnz_out, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_finish (leaf sort + segmented reduce + write)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_us": fin_ms * 1e3, "alg_bytes_per_launch": fin_bytes},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": kernels[dom]["traffic"],
+                     "avg_launch_us": kernels[dom]["avg_launch_us"],
+                     "alg_bytes_per_launch": kernels[dom]["alg_bytes_per_launch"]},
+        "kernels": kernels,
         "step_effective_GBps": eff,
         "per_step_wall_ms": wall * 1e3 / K,
         "first_call_ms": first_call_ms,
