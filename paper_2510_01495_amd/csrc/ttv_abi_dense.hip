@@ -38,7 +38,15 @@ struct Pass {
   size_t lds = 0;
   int grid = 1;
   long long acc_total = 0;
+  size_t tile = 0;  // LDS of a block besides its accumulators
 };
+
+// Tile LDS of the dense kernel for this tensor: the row stage, plus the sort
+// buffers of the compensated-FP32 form.
+size_t tile_lds_of(const ttv_coo_desc* X) {
+  return dense_tile_lds(X->value_dtype == TTV_F64 ? kF64 : kC32, X->index_dtype == TTV_I64 ? 1 : 0,
+                        row_width_class(X->order, X->stride_e, X->stride_j));
+}
 
 void finish_pass(Pass& p, long long nnz) {
   size_t acc = 0;
@@ -47,7 +55,7 @@ void finish_pass(Pass& p, long long nnz) {
     acc += acc_lds(p.nk[q]);
     p.acc_total += p.nk[q];
   }
-  p.lds = acc + dense_tile_lds();
+  p.lds = acc + p.tile;
   const int bpc = (int)std::max<size_t>(1, std::min<size_t>(4, kLdsPerCU / std::max<size_t>(p.lds, 1)));
   const long long ntiles = std::max<long long>(1, (nnz + kTile - 1) / kTile);
   p.grid = (int)std::max<long long>(1, std::min<long long>((long long)kAssumedCUs * bpc, ntiles));
@@ -61,19 +69,22 @@ void plan_passes(const ttv_coo_desc* X, const int* modes, int nm, bool grad_vals
                  int* fallback, int& nfb) {
   npass = 0;
   nfb = 0;
+  const size_t tile = tile_lds_of(X);
   Pass cur;
-  size_t used = dense_tile_lds();
+  cur.tile = tile;
+  size_t used = tile;
   for (int i = 0; i < nm; ++i) {
     const long long nk = X->shape[modes[i]];
     const size_t need = acc_lds(nk);
-    if (need + dense_tile_lds() > kLdsBudget) {
+    if (need + tile > kLdsBudget) {
       fallback[nfb++] = modes[i];
       continue;
     }
     if (cur.nacc == kDenseMaxAcc || used + need > kLdsBudget) {
       passes[npass++] = cur;
       cur = Pass();
-      used = dense_tile_lds();
+      cur.tile = tile;
+      used = tile;
     }
     cur.mode[cur.nacc] = modes[i];
     cur.nk[cur.nacc] = nk;
@@ -82,7 +93,10 @@ void plan_passes(const ttv_coo_desc* X, const int* modes, int nm, bool grad_vals
   }
   if (cur.nacc > 0) passes[npass++] = cur;
   if (grad_vals) {
-    if (npass == 0) passes[npass++] = Pass();  // a pass for the per-nonzero gradient only
+    if (npass == 0) {  // a pass for the per-nonzero gradient only
+      passes[npass] = Pass();
+      passes[npass++].tile = tile;
+    }
     passes[0].grad_vals = true;
   }
   for (int p = 0; p < npass; ++p) finish_pass(passes[p], X->nnz);
@@ -150,7 +164,7 @@ int run_pass(const Pass& p, DenseArgs A, char* ws, size_t part_off, void* const*
   A.partials = reinterpret_cast<double*>(ws + part_off);
   A.err = reinterpret_cast<int32_t*>(ws + offsetof(Ctrl, error));
   A.out_f64 = out_f64;
-  const size_t lds = A.acc_bytes + dense_tile_lds();
+  const size_t lds = A.acc_bytes + p.tile;
   return launch_dense(A, idx64, form, p.grid, lds, s);
 }
 

@@ -38,7 +38,7 @@ struct DenseArgs {
   int out_f64;
 };
 
-size_t dense_tile_lds();
+size_t dense_tile_lds(int form, int idx64, int mo);  // LDS of one block besides its accumulators
 int launch_dense(const DenseArgs& A, int idx64, int form, int grid, size_t lds, hipStream_t s);
 int launch_densify(const void* idx, int idx64, const void* vals, const long long* cnt, void* out, long long n_out,
                    int f64, int cus, hipStream_t s);

@@ -34,17 +34,20 @@ constexpr int IPT = kDenseIPT;
 constexpr int TA = NT * IPT;  // nonzeros per tile
 constexpr int MAXD = 8;       // LDS digit bits
 
-template <typename IdxT, int F>
+template <typename IdxT, int F, int MO, int NACC>
 __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
   using FO = FormOps<F>;
   using Acc = typename FO::Acc;
   using In = typename FO::In;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // layout: accumulators | keys u32[TA] | idx u16[TA] | pay u64[TA] | cnt u32[NW<<MAXD]
+  // layout: accumulators | row stage IdxT[NW][64*MO] | (sort form only) keys u32[TA] | idx u16[TA] |
+  //         pay u64[TA] | cnt u32[NW<<MAXD]
   Acc* accs = reinterpret_cast<Acc*>(smem);
-  unsigned* sk = reinterpret_cast<unsigned*>(smem + A.acc_bytes);
+  IdxT* stage = reinterpret_cast<IdxT*>(smem + A.acc_bytes);
+  unsigned char* sortb = smem + A.acc_bytes + (size_t)NW * 64 * MO * sizeof(IdxT);
+  unsigned* sk = reinterpret_cast<unsigned*>(sortb);
   unsigned short* si = reinterpret_cast<unsigned short*>(sk + TA);
-  uint64_t* sp = reinterpret_cast<uint64_t*>(smem + A.acc_bytes + TA * 4 + TA * 2);
+  uint64_t* sp = reinterpret_cast<uint64_t*>(sortb + TA * 4 + TA * 2);
   unsigned* cnt = reinterpret_cast<unsigned*>(sp + TA);
   __shared__ unsigned wsum[NW];
   __shared__ Seg<F> wagg[NW];
@@ -52,87 +55,96 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
   const unsigned ln = lane_id();
   for (int i = tid; i < A.acc_total; i += NT) accs[i] = FO::zero();
   __syncthreads();
-  const gptr<const IdxT> subs = to_global(static_cast<const IdxT*>(A.subs));
   const gptr<const In> vals = to_global(static_cast<const In*>(A.vals));
+  const bool rowmajor = rows_coalesced(A.order, A.se, A.sj[1]);
   for (long long t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
     const long long e0 = t * TA;
     const int n = (int)((A.nnz - e0 < (long long)TA) ? A.nnz - e0 : (long long)TA);
     // ---- per nonzero: indices of the key modes, products ----
-    unsigned key[kDenseMaxAcc][IPT];
-    uint64_t pay[kDenseMaxAcc][IPT];
+    unsigned key[NACC][IPT];
+    uint64_t pay[NACC][IPT];
     {
       uint64_t full[IPT];  // product of all factors (gradient w.r.t. vals)
-      uint64_t pa[kDenseMaxAcc][IPT];
+      uint64_t pa[NACC][IPT];
       In a[IPT];
+      const int s0 = w * 64 * IPT;  // this wave's slice of the tile
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const int i = w * 64 * IPT + j * 64 + (int)ln;
+        const int i = s0 + j * 64 + (int)ln;
         a[j] = i < n ? vals[e0 + i] : (In)0;
         full[j] = FO::start_prod((In)1);
 #pragma unroll
-        for (int q = 0; q < kDenseMaxAcc; ++q) {
+        for (int q = 0; q < NACC; ++q) {
           pa[q][j] = FO::start_prod(a[j]);
           key[q][j] = 0;
         }
       }
-      for (int m = 0; m < A.order; ++m) {
-        const bool is_key0 = A.nacc > 0 && A.key_mode[0] == m;
-        const bool is_key1 = A.nacc > 1 && A.key_mode[1] == m;
-        const bool is_key2 = A.nacc > 2 && A.key_mode[2] == m;
-        const bool is_key3 = A.nacc > 3 && A.key_mode[3] == m;
-        const In* fac = static_cast<const In*>(A.fac[m]);
-        if (!fac && !(is_key0 || is_key1 || is_key2 || is_key3)) continue;
-        long long x[IPT];
+      long long x[MO][IPT];
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          x[j] = i < n ? (long long)subs[(e0 + i) * A.se + A.sj[m]] : 0;
-          if (A.validate && i < n && (x[j] < 0 || x[j] >= A.dims[m])) {
-            atomicCAS(A.err, 0, TTV_E_INDEX);
-            x[j] = 0;
+      for (int m = 0; m < MO; ++m)
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) x[m][j] = 0;
+      for_rows<IdxT, IPT, MO>(static_cast<const IdxT*>(A.subs), A.se, A.sj[1], A.order, rowmajor, e0 + s0,
+                              (long long)n - s0, stage + (size_t)w * 64 * MO,
+                              [&](int m, int j, long long v) { x[m][j] = v; });
+      if (A.validate) {
+#pragma unroll
+        for (int m = 0; m < MO; ++m)
+#pragma unroll
+          for (int j = 0; j < IPT; ++j)
+            if (m < A.order && s0 + j * 64 + (int)ln < n && (x[m][j] < 0 || x[m][j] >= A.dims[m])) {
+              atomicCAS(A.err, 0, TTV_E_INDEX);
+              x[m][j] = 0;
+            }
+      }
+      // vector entries of every factor mode, gathered together
+      In g[MO][IPT];
+#pragma unroll
+      for (int m = 0; m < MO; ++m) {
+        const In* fac = m < A.order ? static_cast<const In*>(A.fac[m]) : nullptr;
+        const gptr<const In> f = to_global(fac);
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) g[m][j] = (fac && s0 + j * 64 + (int)ln < n) ? f[x[m][j]] : (In)1;
+      }
+#pragma unroll
+      for (int m = 0; m < MO; ++m) {
+        if (m >= A.order) break;
+#pragma unroll
+        for (int q = 0; q < NACC; ++q)
+          if (q < A.nacc && A.key_mode[q] == m) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) key[q][j] = (unsigned)x[m][j];
           }
-        }
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          if (is_key0) key[0][j] = (unsigned)x[j];
-          if (is_key1) key[1][j] = (unsigned)x[j];
-          if (is_key2) key[2][j] = (unsigned)x[j];
-          if (is_key3) key[3][j] = (unsigned)x[j];
-        }
-        if (fac) {
-          const gptr<const In> f = to_global(fac);
-          In g[IPT];
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) g[j] = f[x[j]];
+        if (A.fac[m]) {
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
-            full[j] = FO::mul_prod(full[j], g[j]);
+            full[j] = FO::mul_prod(full[j], g[m][j]);
 #pragma unroll
-            for (int q = 0; q < kDenseMaxAcc; ++q)
-              if (q < A.nacc && A.key_mode[q] != m) pa[q][j] = FO::mul_prod(pa[q][j], g[j]);
+            for (int q = 0; q < NACC; ++q)
+              if (q < A.nacc && A.key_mode[q] != m) pa[q][j] = FO::mul_prod(pa[q][j], g[m][j]);
           }
         }
       }
       if (A.gseg) {
         const gptr<const In> gs = to_global(static_cast<const In*>(A.gseg));
         const gptr<const int32_t> sg = to_global(A.seg);
-        In g[IPT];
+        In h[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          g[j] = i < n ? gs[sg[e0 + i]] : (In)0;
+          const int i = s0 + j * 64 + (int)ln;
+          h[j] = i < n ? gs[sg[e0 + i]] : (In)0;
         }
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-          full[j] = FO::mul_prod(full[j], g[j]);
+          full[j] = FO::mul_prod(full[j], h[j]);
 #pragma unroll
-          for (int q = 0; q < kDenseMaxAcc; ++q) pa[q][j] = FO::mul_prod(pa[q][j], g[j]);
+          for (int q = 0; q < NACC; ++q) pa[q][j] = FO::mul_prod(pa[q][j], h[j]);
         }
       }
       if (A.grad_vals) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
+          const int i = s0 + j * 64 + (int)ln;
           if (i < n) {
             const double v = FO::to_f64(FO::from_pay(full[j]));
             if (F == kF64)
@@ -143,13 +155,34 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < kDenseMaxAcc; ++q)
+      for (int q = 0; q < NACC; ++q)
 #pragma unroll
         for (int j = 0; j < IPT; ++j) pay[q][j] = pa[q][j];
     }
+    if constexpr (F == kF64) {
+      // ---- FP64: LDS atomic adds in nonzero order.  Waves take turns; in a
+      // wave, items in order, and the lanes of one ds_add_f64 that hit the
+      // same entry are applied in ascending lane order (as for the integer
+      // adds the stable ranks rely on).  The block's partial is therefore
+      // the in-order sum of its tiles, bitwise repeatable. ----
+#pragma unroll
+      for (int q = 0; q < NACC; ++q) {
+        if (q >= A.nacc) break;
+        Acc* acc = accs + A.acc_off[q];
+        for (int turn = 0; turn < NW; ++turn) {
+          if (w == turn) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j)
+              if (w * 64 * IPT + j * 64 + (int)ln < n) atomicAdd(&acc[key[q][j]], FO::from_pay(pay[q][j]));
+          }
+          __syncthreads();
+        }
+      }
+      continue;
+    }
     // ---- per accumulator: stable LDS radix sort by key, segmented reduce ----
 #pragma unroll
-    for (int q = 0; q < kDenseMaxAcc; ++q) {
+    for (int q = 0; q < NACC; ++q) {
       if (q >= A.nacc) break;
       Acc* acc = accs + A.acc_off[q];
       const int bits = A.key_bits[q];
@@ -344,12 +377,21 @@ __global__ __launch_bounds__(256) void k_scatter_dense(const IdxT* idx, const do
   }
 }
 
-template <typename IdxT, int F>
-int launch_dense_impl(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
-  hipFuncSetAttribute((const void*)k_dense<IdxT, F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <typename IdxT, int F, int MO, int NACC>
+void launch_dense_k(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
+  hipFuncSetAttribute((const void*)k_dense<IdxT, F, MO, NACC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   prof_begin(TTV_PROF_DENSE, s);
-  hipLaunchKernelGGL((k_dense<IdxT, F>), dim3(grid), dim3(kDenseThreads), lds, s, A);
+  hipLaunchKernelGGL((k_dense<IdxT, F, MO, NACC>), dim3(grid), dim3(kDenseThreads), lds, s, A);
   prof_end(TTV_PROF_DENSE, s);
+}
+
+// one accumulator (the forward all-but-one product) or up to kDenseMaxAcc
+template <typename IdxT, int F, int MO>
+int launch_dense_impl(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
+  if (A.nacc <= 1)
+    launch_dense_k<IdxT, F, MO, 1>(A, grid, lds, s);
+  else
+    launch_dense_k<IdxT, F, MO, kDenseMaxAcc>(A, grid, lds, s);
   const int cb = (int)((A.acc_total + 63) / 64);
   hipLaunchKernelGGL(k_dense_combine, dim3(std::max(cb, 1)), dim3(1024), 0, s, A, grid);
   return 0;
@@ -357,15 +399,29 @@ int launch_dense_impl(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
 
 }  // namespace
 
-size_t dense_tile_lds() { return (size_t)TA * (4 + 2 + 8) + (size_t)(NW << MAXD) * 4; }
+size_t dense_tile_lds(int form, int idx64, int mo) {
+  const size_t stage = (size_t)NW * 64 * mo * (idx64 ? 8 : 4);
+  const size_t sort = form == kF64 ? 0 : (size_t)TA * (4 + 2 + 8) + (size_t)(NW << MAXD) * 4;
+  return stage + sort;
+}
+
+template <typename IdxT, int F>
+int launch_dense_mo(const DenseArgs& A, int mo, int grid, size_t lds, hipStream_t s) {
+  switch (mo) {
+    case 3: return launch_dense_impl<IdxT, F, 3>(A, grid, lds, s);
+    case 5: return launch_dense_impl<IdxT, F, 5>(A, grid, lds, s);
+    default: return launch_dense_impl<IdxT, F, kMaxOrder>(A, grid, lds, s);
+  }
+}
 
 int launch_dense(const DenseArgs& A, int idx64, int form, int grid, size_t lds, hipStream_t s) {
+  const int mo = row_width_class(A.order, A.se, A.sj[1]);
   if (form == kF64) {
-    if (idx64) return launch_dense_impl<long long, kF64>(A, grid, lds, s);
-    return launch_dense_impl<int, kF64>(A, grid, lds, s);
+    if (idx64) return launch_dense_mo<long long, kF64>(A, mo, grid, lds, s);
+    return launch_dense_mo<int, kF64>(A, mo, grid, lds, s);
   }
-  if (idx64) return launch_dense_impl<long long, kC32>(A, grid, lds, s);
-  return launch_dense_impl<int, kC32>(A, grid, lds, s);
+  if (idx64) return launch_dense_mo<long long, kC32>(A, mo, grid, lds, s);
+  return launch_dense_mo<int, kC32>(A, mo, grid, lds, s);
 }
 
 int launch_zero(void* p, size_t bytes, hipStream_t s) {

@@ -256,4 +256,62 @@ __device__ __forceinline__ unsigned long long udiv_magic(unsigned long long n, u
 
 __device__ __forceinline__ int bitlen64(unsigned long long x) { return x ? 64 - __clzll((long long)x) : 0; }
 
+
+// ---------------------------------------------------------------------------
+// Index columns of one round of nonzeros: item j of this lane is nonzero
+// r0 + j*64 + lane, valid while j*64 + lane < nrec (r0 is the first nonzero of
+// the wave's slice); f(m, j, index) is called for every mode m < order.
+//   Row-major rows (se <= MO consecutive indices per nonzero): the wave reads
+//   its slice as consecutive words (every lane one word per load, so a load
+//   covers whole cache lines) and transposes 64 rows at a time through its
+//   LDS stage of 64*MO words.  A lane reading its own row directly touches
+//   64 rows' worth of lines per load for one index each, which caps the read
+//   rate well below HBM bandwidth.
+//   Other strides (structure of arrays): one load per mode, lane-consecutive.
+// ---------------------------------------------------------------------------
+template <typename IdxT, int IPT, int MO, typename Fn>
+__device__ __forceinline__ void for_rows(const IdxT* subs_p, long long se, long long sj, int order, bool rowmajor,
+                                         long long r0, long long nrec, IdxT* stage, Fn&& f) {
+  const gptr<const IdxT> subs = to_global(subs_p);
+  const unsigned ln = lane_id();
+  if (rowmajor) {
+    const long long nr = nrec <= 0 ? 0 : (nrec < 64 * IPT ? nrec : 64 * IPT);
+    const long long wend = nr ? (nr - 1) * se + order : 0;  // the last row's padding is not read
+    const gptr<const IdxT> p = subs + r0 * se;
+    IdxT raw[IPT][MO];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+#pragma unroll
+      for (int c = 0; c < MO; ++c) {
+        const long long wi = (long long)j * 64 * se + c * 64 + ln;
+        raw[j][c] = (c < se && wi < wend) ? p[wi] : (IdxT)0;
+      }
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      wave_lds_sync();
+#pragma unroll
+      for (int c = 0; c < MO; ++c)
+        if (c < se) stage[c * 64 + ln] = raw[j][c];
+      wave_lds_sync();
+#pragma unroll
+      for (int m = 0; m < MO; ++m)
+        if (m < order) f(m, j, (long long)stage[ln * se + m]);
+    }
+    wave_lds_sync();
+  } else {
+#pragma unroll
+    for (int m = 0; m < MO; ++m) {
+      if (m >= order) break;
+      long long x[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const long long i = (long long)j * 64 + ln;
+        x[j] = i < nrec ? (long long)subs[(r0 + i) * se + (long long)m * sj] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) f(m, j, x[j]);
+    }
+  }
+}
+
 }  // namespace ttv

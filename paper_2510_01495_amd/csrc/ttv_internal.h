@@ -137,4 +137,14 @@ struct Layout {
   int32_t count, levels;
 };
 
+// Row class of an index layout: rows of se <= 8 consecutive indices are read
+// whole (row-major), anything else column by column.
+__host__ __device__ inline bool rows_coalesced(int order, long long se, long long sj) {
+  return (order == 1 || sj == 1) && se >= order && se <= kMaxOrder;
+}
+__host__ __device__ inline int row_width_class(int order, long long se, long long sj) {
+  const int need = rows_coalesced(order, se, sj) ? (int)se : order;
+  return need <= 3 ? 3 : (need <= 5 ? 5 : kMaxOrder);
+}
+
 }  // namespace ttv

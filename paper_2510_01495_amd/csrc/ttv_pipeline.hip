@@ -125,7 +125,7 @@ struct RawSrc {
     sj = D.stride_j;
     order = D.order;
     validate = D.validate;
-    rowmajor = (D.order == 1 || D.stride_j == 1) && D.stride_e >= D.order && D.stride_e <= kMaxOrder;
+    rowmajor = rows_coalesced(D.order, D.stride_e, D.stride_j);
     remmask = 0;
 #pragma unroll
     for (int m = 0; m < MO; ++m) {
@@ -151,48 +151,7 @@ struct RawSrc {
 template <typename IdxT, int F, int IPT, int MO, typename Fn>
 __device__ __forceinline__ void for_cols(const RawSrc<IdxT, F, MO>& S, long long r0, long long nrec, IdxT* stage,
                                          Fn&& f) {
-  const gptr<const IdxT> subs = to_global(S.subs);
-  const unsigned ln = lane_id();
-  const int order = S.order;
-  const long long se = S.se;
-  if (S.rowmajor) {
-    const long long nr = nrec <= 0 ? 0 : (nrec < 64 * IPT ? nrec : 64 * IPT);
-    const long long wend = nr ? (nr - 1) * se + order : 0;  // the last row's padding is not read
-    const gptr<const IdxT> p = subs + r0 * se;
-    IdxT raw[IPT][MO];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j)
-#pragma unroll
-      for (int c = 0; c < MO; ++c) {
-        const long long wi = (long long)j * 64 * se + c * 64 + ln;
-        raw[j][c] = (c < se && wi < wend) ? p[wi] : (IdxT)0;
-      }
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      wave_lds_sync();
-#pragma unroll
-      for (int c = 0; c < MO; ++c)
-        if (c < se) stage[c * 64 + ln] = raw[j][c];
-      wave_lds_sync();
-#pragma unroll
-      for (int m = 0; m < MO; ++m)
-        if (m < order) f(m, j, (long long)stage[ln * se + m]);
-    }
-    wave_lds_sync();
-  } else {
-#pragma unroll
-    for (int m = 0; m < MO; ++m) {
-      if (m >= order) break;
-      long long x[IPT];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const long long i = (long long)j * 64 + ln;
-        x[j] = i < nrec ? (long long)subs[(r0 + i) * se + (long long)m * S.sj] : 0;
-      }
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) f(m, j, x[j]);
-    }
-  }
+  for_rows<IdxT, IPT, MO>(S.subs, S.se, S.sj, S.order, S.rowmajor != 0, r0, nrec, stage, f);
 }
 
 template <typename IdxT, int F, int IPT, int MO>
@@ -1458,16 +1417,13 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
 // Register/LDS class of the raw-index loaders: the widest row (stride_e of a
 // row-major tensor, else the order) over the tensors of the run.
 static int row_class(const PipePlan& P) {
-  int need = 1;
-  auto one = [&](const TDesc& D) {
-    const bool rowmajor = (D.order == 1 || D.stride_j == 1) && D.stride_e >= D.order && D.stride_e <= kMaxOrder;
-    need = std::max(need, rowmajor ? (int)D.stride_e : D.order);
-  };
+  int mo = 3;
+  auto one = [&](const TDesc& D) { mo = std::max(mo, row_width_class(D.order, D.stride_e, D.stride_j)); };
   if (P.descs.empty())
     one(P.d0);
   else
     for (const TDesc& D : P.descs) one(D);
-  return need <= 3 ? 3 : (need <= 5 ? 5 : kMaxOrder);
+  return mo;
 }
 
 template <typename IdxT, int F, int PM>
