@@ -1155,14 +1155,92 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         if (j < nj && i < n) atomicOr(&cnt[k[j] >> 5], 1u << (k[j] & 31u));
       }
       __syncthreads();
+      // popcount prefix of the bitmap words (each thread a contiguous run);
+      // with room for it (words <= half the counter space) it is kept after
+      // the bitmap: the rank of a key among the distinct keys is then
+      // wordpre[key / 32] + popcount of the lower bits of its word
+      const bool keep_pre = 2 * words <= (NW << MAXD);
+      const int wpt = (words + NT - 1) / NT;
       unsigned c = 0;
-      for (int q = tid; q < words; q += NT) c += (unsigned)__popc(cnt[q]);
-      block_excl_scan<NT>(c, wsum, u_early);  // its barriers also end the bitmap's use
+      for (int q = tid * wpt; q < words && q < (tid + 1) * wpt; ++q) c += (unsigned)__popc(cnt[q]);
+      unsigned ex = block_excl_scan<NT>(c, wsum, u_early);  // its barriers also end the bitmap's use
+      if (keep_pre) {
+        for (int q = tid * wpt; q < words && q < (tid + 1) * wpt; ++q) {
+          cnt[words + q] = ex;
+          ex += (unsigned)__popc(cnt[q]);
+        }
+      }
       if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u_early);
       // the look-back's first window is read now and used after the sort
       if (w == 0 && !first) {
         const int jp = r - 1 - (int)ln;
         lb_early = jp >= 0 ? __hip_atomic_load(&S[jp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagInc;
+      }
+      if constexpr (F == kF64 && PM == kPipeTTV) {
+        if (keep_pre) {
+          // ---- sort-free FP64 leaf: every record knows its output row (the
+          // rank of its key); each row's sum is built at the position of its
+          // first record, the others adding in leaf order (waves in turn,
+          // items in order, same-entry lanes of one ds_add_f64 in lane
+          // order), so the sum is the in-order sum, bitwise repeatable. ----
+          unsigned* firstpos = sk;  // per row: leaf position of its first record
+          unsigned short* rkey = si;  // per row: its relative key (bits <= 16 here)
+          double* acc = reinterpret_cast<double*>(spay);
+          for (int q = tid; q < (int)u_early; q += NT) firstpos[q] = 0xffffffffu;
+          __syncthreads();  // also orders the prefix words before their reads
+          unsigned row[IPT];
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            const int i = w * 64 * nj + j * 64 + (int)ln;
+            row[j] = 0;
+            if (j < nj && i < n) {
+              const unsigned kk = k[j], wi = kk >> 5;
+              row[j] = cnt[words + wi] + (unsigned)__popc(cnt[wi] & ((1u << (kk & 31u)) - 1u));
+              atomicMin(&firstpos[row[j]], (unsigned)i);
+            }
+          }
+          __syncthreads();
+          bool dup[IPT];
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            const int i = w * 64 * nj + j * 64 + (int)ln;
+            dup[j] = false;
+            if (j < nj && i < n) {
+              if (firstpos[row[j]] == (unsigned)i)
+                rkey[row[j]] = (unsigned short)k[j];
+              else
+                dup[j] = true;
+            }
+          }
+          if (u_early < (unsigned)n) {  // some key repeats: in-order adds
+            for (int turn = 0; turn < NW; ++turn) {
+              if (w == turn) {
+#pragma unroll
+                for (int j = 0; j < IPT; ++j) {
+                  const int i = w * 64 * nj + j * 64 + (int)ln;
+                  if (dup[j]) atomicAdd(&acc[firstpos[row[j]]], __longlong_as_double((long long)spay[i]));
+                }
+              }
+              __syncthreads();
+            }
+          } else {
+            __syncthreads();
+          }
+          if (w == 0) {
+            const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early);
+            if (ln == 0) {
+              if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u_early));
+              s_prefix = prefix;
+              if (last && out_nnz) *out_nnz = prefix + u_early;
+            }
+          }
+          __syncthreads();
+          const long long prefix = s_prefix;
+          for (int q = tid; q < (int)u_early; q += NT)
+            O.write(prefix + q, Lf.base + rkey[q], acc[firstpos[q]]);
+          __syncthreads();
+          continue;
+        }
       }
     }
     const int npass = (Lf.bits + MAXD - 1) / MAXD;
