@@ -467,9 +467,8 @@ __device__ __forceinline__ int block_excl_mm(int v, int ident, int* wsum) {
 // Shared memory of one classify item.
 struct ClassifySmem {
   unsigned s_start[kNDig + 1];
-  int s_bd[kNDig];             // the digit itself if it starts a bucket group, else nd
-  int s_nb[kNDig];             // first group start after the digit
-  unsigned char s_cls[kNDig];  // 0 empty, 1 small, 2 medium, 3 large
+  int s_nb[kNDig];             // the digit if it starts a bucket group (else nd), then the next start after it
+  unsigned char s_cls[kNDig];  // 0 empty, 1 small, 2 medium, 3 large; +4: starts a group
   unsigned wsum[16];
   int wsi[16];
 };
@@ -483,7 +482,6 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
                               ClassifySmem& sm) {
   constexpr int DPT = kNDig / NT;
   unsigned* s_start = sm.s_start;
-  int* s_bd = sm.s_bd;
   int* s_nb = sm.s_nb;
   unsigned char* s_cls = sm.s_cls;
   unsigned* wsum = sm.wsum;
@@ -540,22 +538,27 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
         }
         prev = d;
       }
-      s_bd[d] = bnd ? d : nd;
+      s_nb[d] = bnd ? d : nd;
     }
     __syncthreads();
+    for (int q = 0; q < DPT; ++q) {
+      const int d = tid * DPT + q;
+      if (d < nd && s_nb[d] == d) s_cls[d] |= 4;
+    }
     // next group start after each digit (suffix min-scan, done on reversed order)
     const int rt = NT - 1 - tid;  // this thread scans the digits of thread rt, reversed
     int rv = nd;
     for (int q = 0; q < DPT; ++q) {
       const int d = rt * DPT + q;
-      if (d < nd) rv = min(rv, s_bd[d]);
+      if (d < nd) rv = min(rv, s_nb[d]);
     }
     int nxt = block_excl_mm<false>(rv, nd, wsi);  // min over digits of threads > rt
     for (int q = DPT - 1; q >= 0; --q) {
       const int d = rt * DPT + q;
       if (d < nd) {
+        const int here = s_nb[d];
         s_nb[d] = nxt;  // first group start strictly after digit d
-        nxt = min(nxt, s_bd[d]);
+        nxt = min(nxt, here);
       }
     }
     __syncthreads();
@@ -568,16 +571,16 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int d = tid * DPT + q;
-      if (d < dlo || d >= dhi || s_bd[d] != d) continue;
+      if (d < dlo || d >= dhi || !(s_cls[d] & 4)) continue;
       const unsigned szd = s_start[d + 1] - s_start[d];
-      if (s_cls[d] == 3 && J.shift > 0) {
+      if ((s_cls[d] & 3) == 3 && J.shift > 0) {
         if (deeper) {
           c_lj += 1u << 16;
           c_tile += (unsigned)(((unsigned long long)szd + Tnext - 1) / Tnext);
         }
       } else {
         c_lj += 1u;
-        if (s_cls[d] == 3) c_pure += (unsigned)(((unsigned long long)szd + kPureTile - 1) / kPureTile);
+        if ((s_cls[d] & 3) == 3) c_pure += (unsigned)(((unsigned long long)szd + kPureTile - 1) / kPureTile);
       }
     }
     __shared__ long long s_base[4];
@@ -599,10 +602,10 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int d = tid * DPT + q;
-      if (d < dlo || d >= dhi || s_bd[d] != d) continue;
+      if (d < dlo || d >= dhi || !(s_cls[d] & 4)) continue;
       const long long gstart = J.start + s_start[d];
       const unsigned long long dbase = J.prefix | ((unsigned long long)d << J.shift);
-      const int cls = s_cls[d];
+      const int cls = s_cls[d] & 3;
       const unsigned szd = s_start[d + 1] - s_start[d];
       if (cls == 3 && J.shift > 0) {
         const long long size = szd;
@@ -692,8 +695,7 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
 // ---------------------------------------------------------------------------
 template <typename IdxT, int MO>
 struct ScatterSmem {
-  unsigned cursor[kNDig];
-  unsigned wcnt32[4][kNDig / 2];  // per-wave u16 counters, two per word
+  unsigned cursor[kNDig];  // next position of every bucket
   IdxT stage[kScatterThreads / 64][64 * MO];
   unsigned wsum[kScatterThreads / 64];
 };
@@ -727,10 +729,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
   }
   ScatterSmem<IdxT, MO>& ss = smem.sc;
   unsigned* cursor = ss.cursor;
-  auto& wcnt32 = ss.wcnt32;
   auto& stage = ss.stage;
   unsigned* wsum_s = ss.wsum;
-  auto wcnt = [&](int q, unsigned d) -> unsigned { return (wcnt32[q][d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
   const int ntiles = clampi(C->ntiles[level], W.L.tcap);
   const Job* jobs = W.jobs(level);
   const int* tj = W.tiles(level);
@@ -762,12 +762,6 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
       }
     }
     if (threadIdx.x == 0 && J.src == kSrcRaw) rsrc.set(W.desc()[J.tensor]);
-    for (int i = threadIdx.x; i < kNDig / 2; i += kScatterThreads) {
-      wcnt32[0][i] = 0;
-      wcnt32[1][i] = 0;
-      wcnt32[2][i] = 0;
-      wcnt32[3][i] = 0;
-    }
     __syncthreads();
     const long long b = (long long)(t - J.tile0) * T;
     const long long n = (J.size - b < (long long)T) ? J.size - b : (long long)T;
@@ -781,8 +775,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
     gptr<u64x2> gdst = to_global((u64x2*)dst);
     for (long long rb = 0; rb < n; rb += RN) {
       uint64_t key[IPT], pay[IPT];
-      unsigned dg[IPT], rk[IPT];
-      bool first[IPT];
+      unsigned dg[IPT];
       {
         const long long i0 = rb + (long long)w * RW + ln;
         if (srcR) {
@@ -801,52 +794,33 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level
           load_round<IdxT, F, PM, IPT, MO>(S, roff + s0, n - s0, stage[w], C, key, pay);
         }
       }
+      // positions: the waves take turns adding to the bucket cursors; in a
+      // wave, items in order, and the lanes of one LDS atomic that hit the
+      // same cursor are served in lane order, so every bucket receives the
+      // round's records in input order (wave, item, lane)
+      unsigned pos[IPT];
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const long long i = rb + (long long)w * RW + j * 64 + ln;
-        const bool valid = i < n;
-        dg[j] = valid ? (unsigned)(key[j] >> J.shift) & mask : 0u;
-        rk[j] = 0;
-        first[j] = false;
-        if (valid) {
-          // stable rank within the wave: same-address lanes of one LDS
-          // atomic are served in lane order
-          const unsigned hs = (dg[j] & 1u) * 16u;
-          const unsigned old = (atomicAdd(&wcnt32[w][dg[j] >> 1], 1u << hs) >> hs) & 0xffffu;
-          rk[j] = old;
-          first[j] = old == 0;
+      for (int j = 0; j < IPT; ++j) dg[j] = (unsigned)(key[j] >> J.shift) & mask;
+      for (int turn = 0; turn < kScatterThreads / 64; ++turn) {
+        if (w == turn) {
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            const long long i = rb + (long long)w * RW + j * 64 + ln;
+            pos[j] = i < n ? atomicAdd(&cursor[dg[j]], 1u) : 0u;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
-      bool up[IPT];
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
         const long long i = rb + (long long)w * RW + j * 64 + ln;
-        up[j] = false;
         if (i < n) {
-          const unsigned d = dg[j];
-          unsigned lower = 0;
-          for (int q = 0; q < w; ++q) lower += wcnt(q, d);
-          const unsigned pos = cursor[d] + lower + rk[j];
           u64x2 r;
           r.x = key[j];
           r.y = pay[j];
-          gdst[pos] = r;
-          up[j] = first[j] && lower == 0;
+          gdst[pos[j]] = r;
         }
       }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        if (up[j]) {
-          const unsigned d = dg[j];
-          cursor[d] += wcnt(0, d) + wcnt(1, d) + wcnt(2, d) + wcnt(3, d);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < IPT; ++j)
-        if (first[j]) atomicAnd(&wcnt32[w][dg[j] >> 1], ~(0xffffu << ((dg[j] & 1u) * 16u)));
     }
     __syncthreads();
   }
