@@ -704,7 +704,7 @@ struct ScatterSmem {
 // njobs*slices items); the others scatter its tiles.  Neither role reads what
 // the other writes in this launch.
 template <typename IdxT, int F, int PM, int MO>
-__global__ __launch_bounds__(kScatterThreads) void k_scatter(WsView W, int level, int T, int Tnext, int maxlevel,
+__global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(WsView W, int level, int T, int Tnext, int maxlevel,
                                                              int slices, int gc) {
   constexpr int IPT = kScatterIPT;
   constexpr int RW = 64 * IPT;            // records per wave per round
