@@ -269,35 +269,52 @@ __device__ __forceinline__ int bitlen64(unsigned long long x) { return x ? 64 - 
 //   rate well below HBM bandwidth.
 //   Other strides (structure of arrays): one load per mode, lane-consecutive.
 // ---------------------------------------------------------------------------
+// The row-major read, in two steps so that a caller can issue the next
+// round's loads before it consumes the current one: rows_issue loads the
+// words, rows_deliver transposes them and calls f.
+template <typename IdxT, int IPT, int MO>
+__device__ __forceinline__ void rows_issue(const IdxT* subs_p, long long se, int order, long long r0, long long nrec,
+                                           IdxT (&raw)[IPT][MO]) {
+  const unsigned ln = lane_id();
+  const long long nr = nrec <= 0 ? 0 : (nrec < 64 * IPT ? nrec : 64 * IPT);
+  const long long wend = nr ? (nr - 1) * se + order : 0;  // the last row's padding is not read
+  const gptr<const IdxT> p = to_global(subs_p) + r0 * se;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j)
+#pragma unroll
+    for (int c = 0; c < MO; ++c) {
+      const long long wi = (long long)j * 64 * se + c * 64 + ln;
+      raw[j][c] = (c < se && wi < wend) ? p[wi] : (IdxT)0;
+    }
+}
+
+template <typename IdxT, int IPT, int MO, typename Fn>
+__device__ __forceinline__ void rows_deliver(const IdxT (&raw)[IPT][MO], long long se, int order, IdxT* stage,
+                                             Fn&& f) {
+  const unsigned ln = lane_id();
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < MO; ++c)
+      if (c < se) stage[c * 64 + ln] = raw[j][c];
+    wave_lds_sync();
+#pragma unroll
+    for (int m = 0; m < MO; ++m)
+      if (m < order) f(m, j, (long long)stage[ln * se + m]);
+  }
+  wave_lds_sync();
+}
+
 template <typename IdxT, int IPT, int MO, typename Fn>
 __device__ __forceinline__ void for_rows(const IdxT* subs_p, long long se, long long sj, int order, bool rowmajor,
                                          long long r0, long long nrec, IdxT* stage, Fn&& f) {
   const gptr<const IdxT> subs = to_global(subs_p);
   const unsigned ln = lane_id();
   if (rowmajor) {
-    const long long nr = nrec <= 0 ? 0 : (nrec < 64 * IPT ? nrec : 64 * IPT);
-    const long long wend = nr ? (nr - 1) * se + order : 0;  // the last row's padding is not read
-    const gptr<const IdxT> p = subs + r0 * se;
     IdxT raw[IPT][MO];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j)
-#pragma unroll
-      for (int c = 0; c < MO; ++c) {
-        const long long wi = (long long)j * 64 * se + c * 64 + ln;
-        raw[j][c] = (c < se && wi < wend) ? p[wi] : (IdxT)0;
-      }
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      wave_lds_sync();
-#pragma unroll
-      for (int c = 0; c < MO; ++c)
-        if (c < se) stage[c * 64 + ln] = raw[j][c];
-      wave_lds_sync();
-#pragma unroll
-      for (int m = 0; m < MO; ++m)
-        if (m < order) f(m, j, (long long)stage[ln * se + m]);
-    }
-    wave_lds_sync();
+    rows_issue<IdxT, IPT, MO>(subs_p, se, order, r0, nrec, raw);
+    rows_deliver<IdxT, IPT, MO>(raw, se, order, stage, f);
   } else {
 #pragma unroll
     for (int m = 0; m < MO; ++m) {
