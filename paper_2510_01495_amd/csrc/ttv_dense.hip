@@ -237,8 +237,12 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
           const int i = w * 64 * IPT + j * 64 + (int)ln;
           if (i < n) {
             const unsigned dest = cnt[w * nb + ((k[j] >> sh) & dmask)] + rk[j];
-            sk[dest] = k[j];
-            si[dest] = (unsigned short)ix[j];
+            if (dest < (unsigned)n) {  // always, unless the counters are corrupt: then report, never write outside
+              sk[dest] = k[j];
+              si[dest] = (unsigned short)ix[j];
+            } else {
+              atomicCAS(A.err, 0, TTV_E_DEVICE);
+            }
           }
         }
         __syncthreads();

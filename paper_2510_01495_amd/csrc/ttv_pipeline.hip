@@ -1143,6 +1143,9 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           cnt[words + q] = ex;
           ex += (unsigned)__popc(cnt[q]);
         }
+        // the prefix words are written, and the bitmap read, by every thread
+        // before any reuses the counter space (the sort clears it)
+        __syncthreads();
       }
       if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u_early);
       // the look-back's first window is read now and used after the sort
@@ -1264,8 +1267,12 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         if (j < nj && i < n) {
           const unsigned d = wide ? (unsigned)(((R[ix[j]].key - Lf.base) >> sh) & dmask) : (k[j] >> sh) & dmask;
           const unsigned dest = cnt[w * nb + d] + rk[j];
-          sk[dest] = k[j];
-          si[dest] = (unsigned short)ix[j];
+          if (dest < (unsigned)n) {  // always, unless the counters are corrupt: then report, never write outside
+            sk[dest] = k[j];
+            si[dest] = (unsigned short)ix[j];
+          } else {
+            set_error(C, TTV_E_DEVICE);
+          }
         }
       }
       __syncthreads();
@@ -1438,12 +1445,15 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
   for (int l = 1; l <= P.levels; ++l) {
     const int T = l == 1 ? P.T1 : P.T2;
     const int Tn = P.T2;
-    const int gt = l == 1 ? (int)std::max<long long>(1, std::min<long long>(P.tiles1, 8LL * cus)) : 4 * cus;
-    const int gj = l == 1 ? std::max(1, P.count) : 2 * cus;
+    // deeper levels: grids sized for the chip, not for the (unknown) work --
+    // every kernel strides over its items, and an empty level then costs
+    // little more than its launches
+    const int gt = l == 1 ? (int)std::max<long long>(1, std::min<long long>(P.tiles1, 8LL * cus)) : 2 * cus;
+    const int gj = l == 1 ? std::max(1, P.count) : cus;
     if (l == 1) prof_begin(TTV_PROF_HIST1, s);
-    hipLaunchKernelGGL((k_hist<IdxT, MO>), dim3(gt), dim3(kHistThreads), 0, s, W, l, T);
+    hipLaunchKernelGGL((k_hist<IdxT, MO>), dim3(l == 1 ? gt : cus), dim3(kHistThreads), 0, s, W, l, T);
     if (l == 1) prof_end(TTV_PROF_HIST1, s);
-    hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 4 * cus), dim3(1024),
+    hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 2 * cus), dim3(1024),
                        0, s, W, l);
     // classify blocks first (short), then the scatter's tiles
     const int slices = l == 1 ? kClassifySlices : 1;

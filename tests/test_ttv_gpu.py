@@ -245,3 +245,43 @@ def test_zipf_deeper_levels():
     say("zipf 1e6 c32")
     gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_, out_f64=True)
     check_ttv(X, mode, v, gs, gv, C32_TOL, "zipf 1e6")
+
+
+@pytest.mark.gpu
+def test_zipf_c32_repeated_launches():
+    """5e6 Zipf FP32 nonzeros (level-3 single-key buckets, narrow and wide
+    leaves), launched three times on one workspace: every launch reports no
+    device error and gives bitwise the same result; the rows are the distinct
+    remaining-mode tuples in order, and sampled values match the oracle.
+    Regression: the finish's bitmap prefix and the radix sort shared LDS
+    without a barrier between them."""
+    import torch
+    P = _api()
+    X, mode, v = synth.workload_zipf(scale=0.1)
+    subs, vals, gv_ = to_gpu(X, v)
+    op = P.TTVOp(subs, vals, X.shape, [mode], [gv_], out_f64=True)
+    first = None
+    for rep in range(3):
+        say(f"zipf 5e6 c32 launch {rep}")
+        op.launch()
+        torch.cuda.synchronize()
+        assert op.device_error() == 0
+        gs, gv, _ = op.result()
+        got = (gs.cpu().numpy().astype(np.int64), gv.cpu().numpy())
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got[0], first[0]) and np.array_equal(got[1], first[1])
+    gs, gv = first
+    R = [j for j in range(4) if j != mode]
+    dims = [X.shape[j] for j in R]
+    lin = (gs[:, 0] * dims[1] + gs[:, 1]) * dims[2] + gs[:, 2]
+    assert np.all(np.diff(lin) > 0), "rows not strictly increasing"
+    sub = X.subs[:, R].astype(np.int64)
+    want_rows = np.unique((sub[:, 0] * dims[1] + sub[:, 1]) * dims[2] + sub[:, 2]).size
+    assert gs.shape[0] == want_rows
+    pick = np.random.default_rng(7).choice(gs.shape[0], size=200, replace=False)
+    want = oracle.ttv_entries(X.subs, X.vals, X.shape, mode, v, gs[pick])
+    scale = oracle.abs_sums(X.subs, X.vals, X.shape, mode, v, gs[pick])
+    err = np.abs(gv[pick] - want)
+    assert np.all(err <= C32_TOL * scale + 1e-300), float(np.max(err / scale))
