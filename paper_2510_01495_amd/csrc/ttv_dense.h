@@ -8,8 +8,8 @@
 
 namespace ttv {
 
-constexpr int kDenseThreads = 512;
-constexpr int kDenseIPT = 4;
+constexpr int kDenseThreads = 1024;
+constexpr int kDenseIPT = 2;
 constexpr int kDenseMaxAcc = 4;
 
 struct DenseArgs {
