@@ -230,6 +230,39 @@ int ttv_batch_autotune(ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_stre
 int ttv_coo_batched(const ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_stream_t stream);
 void ttv_batch_plan_destroy(ttv_batch_plan* plan);
 
+/* ------------------------------------------------------------------------
+ * Repeated TTV with a fixed tensor and mode (Eq. 3 applied to a new vector
+ * each call, as iterative methods do).  The keyed sort runs once, in setup;
+ * every apply is then one streaming pass over the nonzeros in output order
+ * (product and segmented sum), without sorting.
+ *   ttv_reuse_plan_create  host only: validates X and mode (as ttv_coo) and
+ *                          sizes the buffers; X's arrays must stay valid until
+ *                          setup has run on the stream.
+ *   ttv_reuse_sizes        bytes of the persistent plan buffer `data` (kept
+ *                          by the caller as long as the plan is applied) and
+ *                          of the setup workspace (free after setup).
+ *   ttv_reuse_setup        sorts X: writes the output coordinates out_subs
+ *                          (capacity nnz x (d-1), X's index type) and out_nnz
+ *                          (device int64), and fills `data` with the values
+ *                          and contracted-mode indices in output order and
+ *                          every position's output row.  Device errors are
+ *                          read with ttv_check_device_error(ws, stream).
+ *   ttv_reuse_apply        out_vals[r] = output row r of ttv_coo(X, mode, v)
+ *                          (capacity nnz values: FP64, or FP32 for TTV_F32
+ *                          unless the plan was made with TTV_OUT_F64).  Reads
+ *                          only `data` and v; no workspace, no allocation, no
+ *                          host synchronisation.  Each sum is formed in one
+ *                          fixed order (bitwise repeatable), not ttv_coo's.
+ * ---------------------------------------------------------------------- */
+typedef struct ttv_reuse_plan ttv_reuse_plan;
+int ttv_reuse_plan_create(const ttv_coo_desc* X, int32_t mode, int32_t flags, ttv_reuse_plan** plan);
+int ttv_reuse_sizes(const ttv_reuse_plan* plan, size_t* data_bytes, size_t* setup_ws_bytes);
+int ttv_reuse_setup(ttv_reuse_plan* plan, void* data, size_t data_bytes, void* out_subs,
+                    int64_t* out_nnz, void* ws, size_t ws_bytes, ttv_stream_t stream);
+int ttv_reuse_apply(const ttv_reuse_plan* plan, const void* v, int64_t v_len, void* out_vals,
+                    ttv_stream_t stream);
+void ttv_reuse_plan_destroy(ttv_reuse_plan* plan);
+
 /*
  * Measurement hook.  While set, the library records the caller's HIP events
  * starts[k] / stops[k] on the launch stream around the k-th launch of one of
@@ -237,10 +270,18 @@ void ttv_batch_plan_destroy(ttv_batch_plan* plan);
  * recorded), so a benchmark can time that kernel inside its timed region.
  * kernel: TTV_PROF_NONE disables; TTV_PROF_FINISH the leaf sort-reduce-write
  * kernel; TTV_PROF_SCATTER1 the first-level bucket scatter; TTV_PROF_HIST1
- * its histogram; TTV_PROF_DENSE the dense accumulation kernel.  Not
- * thread-safe; for measurement only.  ttv_profile_count returns k.
+ * its histogram; TTV_PROF_DENSE the dense accumulation kernel;
+ * TTV_PROF_REUSE the streaming kernel of ttv_reuse_apply.  Not thread-safe;
+ * for measurement only.  ttv_profile_count returns k.
  */
-enum { TTV_PROF_NONE = 0, TTV_PROF_FINISH = 1, TTV_PROF_SCATTER1 = 2, TTV_PROF_HIST1 = 3, TTV_PROF_DENSE = 4 };
+enum {
+  TTV_PROF_NONE = 0,
+  TTV_PROF_FINISH = 1,
+  TTV_PROF_SCATTER1 = 2,
+  TTV_PROF_HIST1 = 3,
+  TTV_PROF_DENSE = 4,
+  TTV_PROF_REUSE = 5
+};
 int ttv_profile_events(int32_t kernel, void* const* starts, void* const* stops, int32_t capacity);
 int ttv_profile_count(void);
 

@@ -10,6 +10,7 @@ from . import _lib  # noqa: F401
 from .api import (  # noqa: F401
     AllButOp,
     BatchedTTV,
+    ReuseTTV,
     TTVAllButFunction,
     TTVFunction,
     TTVOp,
@@ -21,5 +22,5 @@ from .api import (  # noqa: F401
     ttv_multi,
 )
 
-__all__ = ["AllButOp", "BatchedTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc", "plan_query", "ttv",
+__all__ = ["AllButOp", "BatchedTTV", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc", "plan_query", "ttv",
            "ttv_allbut", "ttv_backward", "ttv_multi"]

@@ -17,7 +17,7 @@ I32, I64 = 0, 1
 F32, F64 = 0, 1
 VALIDATE, OUT_F64 = 0x1, 0x2
 BWD_SPARSE, BWD_ALLBUT = 0, 1
-PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE = 0, 1, 2, 3, 4
+PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE, PROF_REUSE = 0, 1, 2, 3, 4, 5
 
 
 class CooDesc(ctypes.Structure):
@@ -64,6 +64,12 @@ SIGNATURES = {
     "ttv_batch_autotune": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "ttv_coo_batched": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "ttv_batch_plan_destroy": (None, [c_void_p]),
+    "ttv_reuse_plan_create": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_void_p)]),
+    "ttv_reuse_sizes": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
+    "ttv_reuse_setup": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_size_t,
+                                  c_void_p]),
+    "ttv_reuse_apply": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "ttv_reuse_plan_destroy": (None, [c_void_p]),
     "ttv_check_device_error": (c_int32, [c_void_p, c_void_p]),
     "ttv_profile_events": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p), c_int32]),
     "ttv_profile_count": (c_int32, []),

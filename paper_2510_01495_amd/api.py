@@ -364,3 +364,58 @@ class BatchedTTV:
                 self.plan = c_void_p()
         except Exception:
             pass
+
+
+class ReuseTTV:
+    """Repeated sparse TTV of one tensor in one mode with a new vector each
+    call.  The constructor sorts the tensor once (the output coordinates
+    ``out_subs[:nnz_out]`` are fixed from then on); ``apply(v)`` enqueues one
+    streaming pass that writes ``out_vals`` and returns without synchronising;
+    ``result()`` synchronises and slices.  The tensor's arrays are not needed
+    after the constructor returns."""
+
+    def __init__(self, subs, vals, shape, mode: int, *, flags: int = 0, out_f64: bool = False):
+        self.lib = L.load()
+        self.shape = tuple(int(s) for s in shape)
+        self.mode = int(mode)
+        self.flags = flags | (L.OUT_F64 if out_f64 else 0)
+        self.vdtype = vals.dtype
+        desc = coo_desc(subs, vals, self.shape)
+        self.plan = c_void_p()
+        L.check(self.lib.ttv_reuse_plan_create(byref(desc), self.mode, self.flags, byref(self.plan)),
+                "ttv_reuse_plan_create")
+        nd, nw = c_size_t(0), c_size_t(0)
+        L.check(self.lib.ttv_reuse_sizes(self.plan, byref(nd), byref(nw)), "ttv_reuse_sizes")
+        dev = subs.device
+        nnz, d = subs.shape[0], len(self.shape)
+        self.data = torch.empty(max(1, nd.value), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(1, nw.value), dtype=torch.uint8, device=dev)
+        self.out_subs = torch.empty((max(nnz, 1), d - 1), dtype=subs.dtype, device=dev)
+        self.out_vals = torch.empty(max(nnz, 1), dtype=_out_value_dtype(vals, out_f64), device=dev)
+        self.out_nnz = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.newshape = tuple(s for j, s in enumerate(self.shape) if j != self.mode)
+        L.check(self.lib.ttv_reuse_setup(self.plan, self.data.data_ptr(), self.data.numel(),
+                                         self.out_subs.data_ptr(), self.out_nnz.data_ptr(), ws.data_ptr(),
+                                         ws.numel(), _stream(dev)), "ttv_reuse_setup")
+        L.check(self.lib.ttv_check_device_error(ws.data_ptr(), _stream(dev)), "device")
+        self.nnz_out = int(self.out_nnz.item())
+        self.v = None
+
+    def apply(self, v):
+        _check_tensor(v, "v")
+        if v.dtype != self.vdtype:
+            raise TypeError("v must have the dtype of vals")
+        self.v = v.contiguous()  # kept alive until the next apply
+        L.check(self.lib.ttv_reuse_apply(self.plan, self.v.data_ptr(), self.v.numel(), self.out_vals.data_ptr(),
+                                         _stream(self.out_vals.device)), "ttv_reuse_apply")
+
+    def result(self):
+        torch.cuda.synchronize(self.out_vals.device)
+        m = self.nnz_out
+        return self.out_subs[:m], self.out_vals[:m], self.newshape
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan is not None and plan.value:
+            self.lib.ttv_reuse_plan_destroy(plan)
+            self.plan = None

@@ -45,6 +45,8 @@ enum Src : int32_t { kSrcRaw = 0, kSrcA = 1, kSrcB = 2 };
 enum PipeMode : int32_t {
   kPipeTTV = 0,     // sparse output: coordinates + summed values
   kPipeSegMap = 1,  // no values: for every input nonzero, the output row it lands in
+  kPipePerm = 2,    // no values: output coordinates, and for every sorted position the
+                    // nonzero there (perm_out) and its output row (seg_out)
 };
 
 struct Rec {
@@ -60,7 +62,8 @@ struct TDesc {
   void* out_subs;               // (nnz_out, nrem) row-major, index dtype of the input
   void* out_vals;               // nnz_out values
   long long* out_nnz;           // device scalar
-  int32_t* seg_out;             // segment map (kPipeSegMap)
+  int32_t* seg_out;             // segment map (kPipeSegMap); output row per sorted position (kPipePerm)
+  int32_t* perm_out;            // nonzero per sorted position (kPipePerm)
   const void* segfac;           // optional factor of every payload, gathered through segidx
   const int32_t* segidx;
   long long nnz;

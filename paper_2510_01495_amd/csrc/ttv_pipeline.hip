@@ -179,7 +179,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long lo
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const long long i = (long long)j * 64 + ln;
-    a[j] = (PM != kPipeSegMap && i < nrec) ? vals[r0 + i] : (In)0;
+    a[j] = (PM == kPipeTTV && i < nrec) ? vals[r0 + i] : (In)0;
   }
   long long x[MO][IPT];
   fetch_cols<IdxT, F, IPT, MO>(S, r0, nrec, stage, x);
@@ -196,7 +196,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long lo
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     key[j] = 0;
-    pay[j] = PM == kPipeSegMap ? (uint64_t)(r0 + (long long)j * 64 + ln) : FO::start_prod(a[j]);
+    pay[j] = PM != kPipeTTV ? (uint64_t)(r0 + (long long)j * 64 + ln) : FO::start_prod(a[j]);
   }
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
@@ -207,7 +207,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long lo
       for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[m][j] * st;
     }
   }
-  if (PM == kPipeSegMap) return;
+  if (PM != kPipeTTV) return;
   In g[MO][IPT];
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
@@ -1002,6 +1002,13 @@ struct OutInfo {
   }
   // unpack the mixed-radix key into the remaining indices, then the value
   __device__ __forceinline__ void write(long long row, uint64_t key, double v) const {
+    write_subs(row, key);
+    if (f64out)
+      v64[row] = v;
+    else
+      v32[row] = (float)v;
+  }
+  __device__ __forceinline__ void write_subs(long long row, uint64_t key) const {
     gptr<IdxT> o = subs + row * nrem;
     unsigned long long k = key;
     // kept rolled: the constants stay in LDS instead of pinning registers
@@ -1012,10 +1019,6 @@ struct OutInfo {
       k -= q * kst[i];
     }
     o[nrem - 1] = (IdxT)k;  // the last stride is 1
-    if (f64out)
-      v64[row] = v;
-    else
-      v32[row] = (float)v;
   }
 };
 
@@ -1080,6 +1083,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           const double* P = W.partials() + Lf.ptile0;
           for (int k = 0; k < Lf.nptiles; ++k) v += P[k];
           if (PM == kPipeTTV) O.write(prefix, Lf.base, v);
+          if (PM == kPipePerm) O.write_subs(prefix, Lf.base);
           if (last && out_nnz) *out_nnz = prefix + 1;
         }
       }
@@ -1087,6 +1091,16 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         __syncthreads();
         const long long row = s_prefix;
         for (long long i = tid; i < Lf.size; i += NT) seg_out[(long long)R[i].pay] = (int32_t)row;
+      }
+      if (PM == kPipePerm) {  // every record of the run, in record order
+        __syncthreads();
+        const long long row = s_prefix;
+        const long long pos0 = Lf.start - D.base;
+        gptr<int32_t> perm_out = to_global(D.perm_out);
+        for (long long i = tid; i < Lf.size; i += NT) {
+          perm_out[pos0 + i] = (int32_t)R[i].pay;
+          seg_out[pos0 + i] = (int32_t)row;
+        }
       }
       __syncthreads();
       continue;
@@ -1409,6 +1423,14 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         const long long rowi = prefix + hrun + upto - 1;
         if (PM == kPipeSegMap) {
           seg_out[(long long)spay[si[p]]] = (int32_t)rowi;
+        } else if (PM == kPipePerm) {
+          // sorted position -> nonzero and output row; the run's last record
+          // writes the row's coordinates
+          const long long pos = Lf.start - D.base + p;
+          to_global(D.perm_out)[pos] = (int32_t)spay[si[p]];
+          seg_out[pos] = (int32_t)rowi;
+          const bool end = p == n - 1 || (wide ? R[si[p + 1]].key != R[si[p]].key : sk[p + 1] != sk[p]);
+          if (end) O.write_subs(rowi, wide ? R[si[p]].key : Lf.base + sk[p]);
         } else {
           bool end;
           if (p == n - 1)
@@ -1499,6 +1521,8 @@ static int launch_mo(const PipePlan& P, void* ws, hipStream_t s) {
 
 int launch_pipeline(const PipePlan& P, void* ws, hipStream_t s) {
   const bool i64 = P.idx64 != 0;
+  if (P.pipe_mode == kPipePerm)  // records carry nonzero indices: the value form does not matter
+    return i64 ? launch_mo<long long, kF64, kPipePerm>(P, ws, s) : launch_mo<int, kF64, kPipePerm>(P, ws, s);
   if (P.pipe_mode == kPipeSegMap) {
     if (P.form == kF64)
       return i64 ? launch_mo<long long, kF64, kPipeSegMap>(P, ws, s) : launch_mo<int, kF64, kPipeSegMap>(P, ws, s);

@@ -110,3 +110,34 @@ def test_workspace_queries():
     for kind in (0, 1):
         assert lib.ttv_coo_backward_workspace(ctypes.byref(d), kind, 0, 0, ctypes.byref(nb)) == 0
     assert lib.ttv_coo_backward_workspace(ctypes.byref(d), 5, 0, 0, ctypes.byref(nb)) == -12
+
+
+def test_reuse_plan_host_checks():
+    """Repeated-TTV plans: argument checks and buffer sizes, host only."""
+    L, lib = _lib()
+    E = dict(NULL=-1, ORDER=-2, MODE=-3, SHAPE=-4, WORKSPACE=-7, ARG=-12)
+    plan = ctypes.c_void_p()
+    assert lib.ttv_reuse_plan_create(ctypes.byref(_desc((5, 6, 7), 3)), 3, 0, ctypes.byref(plan)) == E["MODE"]
+    assert not plan.value
+    assert lib.ttv_reuse_plan_create(ctypes.byref(_desc((5,), 3)), 0, 0, ctypes.byref(plan)) == E["ORDER"]
+    assert lib.ttv_reuse_plan_create(ctypes.byref(_desc((5, 6, 7), 3)), 0, 0, None) == E["NULL"]
+    nnz = 10_000_000
+    d = _desc((10_000,) * 3, nnz)  # int64, FP64
+    assert lib.ttv_reuse_plan_create(ctypes.byref(d), 1, 0, ctypes.byref(plan)) == 0 and plan.value
+    try:
+        nd, nw = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        assert lib.ttv_reuse_sizes(plan, ctypes.byref(nd), ctypes.byref(nw)) == 0
+        # values, contracted indices and output rows of every nonzero, plus per-chunk carries
+        assert nnz * (8 + 8 + 4) <= nd.value <= nnz * (8 + 8 + 4) + 2 * 16 * (nnz // 4096 + 1) + 4096
+        ws_pipe = ctypes.c_size_t(0)
+        assert lib.ttv_coo_workspace(ctypes.byref(d), 1, 0, ctypes.byref(ws_pipe)) == 0
+        assert nw.value >= ws_pipe.value + 4 * nnz  # the pipeline, then the permutation
+        v = ctypes.c_void_p(1)
+        # apply before setup; setup with buffers too small: rejected before anything is enqueued
+        assert lib.ttv_reuse_apply(plan, v, 10_000, v, None) == E["ARG"]
+        assert lib.ttv_reuse_setup(plan, v, 16, v, v, v, nw.value, None) == E["WORKSPACE"]
+        assert lib.ttv_reuse_setup(plan, v, nd.value, v, v, v, 16, None) == E["WORKSPACE"]
+        assert lib.ttv_reuse_setup(plan, v, nd.value, v, None, v, nw.value, None) == E["NULL"]
+    finally:
+        lib.ttv_reuse_plan_destroy(plan)
+    lib.ttv_reuse_plan_destroy(None)  # a null plan is ignored
