@@ -94,8 +94,8 @@ def reuse_comparison(X, subs, vals, v, K, ttv_us):
     """Repeated TTV (fixed tensor and mode 0, new vector per call): setup once,
     then K applies timed with events, the streaming kernel with the
     library's per-launch events; algorithmic bytes per apply are the values,
-    contracted indices and output rows of every nonzero read once and every
-    output value written once."""
+    32-bit contracted indices and row-start bits of every nonzero and the
+    vector read once, and every output value written once."""
     import numpy as np
     import torch
     from ctypes import c_void_p
@@ -129,7 +129,7 @@ def reuse_comparison(X, subs, vals, v, K, ttv_us):
     gs, gv, _ = R.result()
     err = sampled_error(X, 0, v.cpu().numpy(), gs, gv, 100, 5)
     nnz, nout = X.nnz, R.nnz_out
-    alg = nnz * (8 + 8 + 4) + nout * 8 + X.shape[0] * 8
+    alg = nnz * (8 + 4) + nnz / 8 + nout * 8 + X.shape[0] * 8
     return {"mode": 0, "setup_ms": setup_ms, "ms_per_apply": apply_ms, "nnz_per_s": nnz / (apply_ms * 1e-3),
             "speedup_vs_ttv": ttv_us / (apply_ms * 1e3), "max_rel_err_sampled": err,
             "kernel": {"name": "k_reuse_apply", "avg_launch_us": kern_ms * 1e3, "alg_bytes_per_launch": alg,

@@ -244,9 +244,13 @@ void ttv_batch_plan_destroy(ttv_batch_plan* plan);
  *   ttv_reuse_setup        sorts X: writes the output coordinates out_subs
  *                          (capacity nnz x (d-1), X's index type) and out_nnz
  *                          (device int64), and fills `data` with the values
- *                          and contracted-mode indices in output order and
- *                          every position's output row.  Device errors are
- *                          read with ttv_check_device_error(ws, stream).
+ *                          and contracted-mode indices in output order
+ *                          (indices as uint32 when the mode's length is at
+ *                          most 2^32), one bit per position marking where an
+ *                          output row starts, and each 512-position chunk's
+ *                          first row: about 8 + 4 + 1/8 bytes per nonzero for
+ *                          FP64 values.  Device errors are read with
+ *                          ttv_check_device_error(ws, stream).
  *   ttv_reuse_apply        out_vals[r] = output row r of ttv_coo(X, mode, v)
  *                          (capacity nnz values: FP64, or FP32 for TTV_F32
  *                          unless the plan was made with TTV_OUT_F64).  Reads

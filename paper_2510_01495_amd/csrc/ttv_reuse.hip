@@ -5,12 +5,15 @@
 // Setup runs the sorting pipeline in its permutation mode: it writes the
 // output coordinates (which do not depend on the vector) and, for every
 // position of the sorted order, the nonzero there and its output row.  A
-// gather then stores the values and the contracted-mode indices in sorted
-// order in the caller's plan buffer.
+// gather then stores in the caller's plan buffer, in sorted order, the values
+// and the contracted-mode indices (32-bit when the mode's length allows), one
+// bit per position marking the first position of every output row, and the
+// output row of every chunk's first position.
 //
 // Each apply is one streaming pass over that buffer: per sorted position the
 // product value x v[index], and a segmented sum over runs of equal output
-// row.  Chunks of kReuseChunk positions are reduced by one block each
+// row (a run starts at a marked position; a row's number is the chunk's first
+// row plus the marks counted since).  Chunks of kReuseChunk positions are reduced by one block each
 // (in-wave DPP segmented scans, carried across rounds and waves in order);
 // rows inside a chunk are written directly, and the partial sums of a
 // chunk's first and last rows are combined by a second kernel in chunk
@@ -22,6 +25,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "ttv.h"
 #include "ttv_device.hpp"
@@ -37,52 +41,116 @@ struct ttv_reuse_plan {
   int out_f64 = 1;
   long long nnz = 0;
   long long nchunks = 0;
-  size_t off_sv = 0, off_sidx = 0, off_rowid = 0, off_carry = 0, data_bytes = 0;
-  size_t off_perm = 0, setup_bytes = 0;  // setup workspace: pipeline, then the permutation
+  int sidx32 = 1;  // contracted-mode indices stored as uint32 (the mode's length is at most 2^32)
+  size_t off_sv = 0, off_sidx = 0, off_heads = 0, off_row0 = 0, off_groups = 0, off_carry = 0, data_bytes = 0;
+  size_t off_perm = 0, off_rowid = 0, setup_bytes = 0;  // setup workspace: pipeline, permutation, rows
   void* data = nullptr;                  // bound by setup
+  int cus = 0;                           // compute units of the setup's device
 };
 
 namespace ttv {
 namespace {
 
-constexpr int kReuseThreads = 512;
+constexpr int kReuseThreads = 256;                      // 4 waves, each with its own chunk
+constexpr int kReuseLdsThreads = 1024;                  // v staged in LDS: 16 waves looping over chunks
 constexpr int kReuseIPT = 8;
-constexpr int kReuseChunk = kReuseThreads * kReuseIPT;  // sorted positions per block
+constexpr int kReuseChunk = 64 * kReuseIPT;             // sorted positions per wave
 constexpr size_t kReuseHdr = 256;                       // int64 nnz_out at offset 0
+constexpr size_t kReuseMaxVLds = 128 * 1024;            // largest vector staged in LDS
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct Carry {
-  long long row;  // -1: unused
-  double val;
+// Carry entry e of the apply: 2c holds chunk c's first run's partial sum,
+// 2c+1 its last run's (unused when the chunk holds a single run).  Groups
+// are fixed by the plan: for an entry that opens an output row (no used entry
+// of the same row before it), the row and how many following entries belong
+// to it (entry 2c of every following chunk c whose first row is the same).
+struct Group {
+  long long row;  // -1: the entry opens no row
+  long long cnt;
 };
 
-// sv[k] = vals[perm[k]], sidx[k] = subs(perm[k], mode); the header gets nnz_out.
-template <typename IdxT, typename In>
+// sv[k] = vals[perm[k]], sidx[k] = subs(perm[k], mode); heads bit k set when
+// sorted position k starts an output row; row0[c] = output row of position
+// c * kReuseChunk; the header gets nnz_out.  One wave per 64 positions.
+template <typename IdxT, typename In, typename SIdx>
 __global__ __launch_bounds__(256) void k_reuse_gather(const IdxT* subs, long long se, long long sjm, const In* vals,
-                                                      const int32_t* perm, long long nnz, In* sv, IdxT* sidx,
-                                                      const long long* out_nnz, long long* hdr) {
+                                                      const int32_t* perm, const int32_t* rowid, long long nnz,
+                                                      In* sv, SIdx* sidx, unsigned long long* heads,
+                                                      long long* row0, const long long* out_nnz, long long* hdr) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *hdr = *out_nnz;
   const gptr<const IdxT> gs = to_global(subs);
   const gptr<const In> gv = to_global(vals);
   const gptr<const int32_t> gp = to_global(perm);
-  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
-       k += (long long)gridDim.x * blockDim.x) {
-    const long long e = gp[k];
-    sv[k] = gv[e];
-    sidx[k] = gs[e * se + sjm];
+  const gptr<const int32_t> gr = to_global(rowid);
+  const unsigned ln = lane_id();
+  const long long nw = (nnz + 63) / 64;
+  const long long tw = (long long)gridDim.x * (blockDim.x / 64);
+  for (long long q = (long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < nw; q += tw) {
+    const long long k = q * 64 + ln;
+    bool h = false;
+    if (k < nnz) {
+      const long long e = gp[k];
+      sv[k] = gv[e];
+      sidx[k] = (SIdx)gs[e * se + sjm];
+      const int32_t r = gr[k];
+      h = k == 0 || r != gr[k - 1];
+      if (k % kReuseChunk == 0) row0[k / kReuseChunk] = r;
+    }
+    const uint64_t m = ballot(h);
+    if (ln == 0) heads[q] = m;
   }
+}
+
+// The carry groups, from the output row of every sorted position.
+__global__ __launch_bounds__(256) void k_reuse_groups(const int32_t* rowid, const long long* row0, long long nnz,
+                                                      long long nchunks, Group* groups) {
+  const gptr<const int32_t> gr = to_global(rowid);
+  const long long E = 2 * nchunks;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long c = e >> 1, k0 = c * kReuseChunk;
+    const long long n = std::min<long long>(kReuseChunk, nnz - k0);
+    const long long first = gr[k0], last = gr[k0 + n - 1];
+    const long long r = (e & 1) ? (last != first ? last : -1) : first;
+    // the previous used entry's row: entry 2c's for entry 2c+1, else the
+    // previous chunk's last row
+    const long long prev = (e & 1) ? first : (c > 0 ? (long long)gr[k0 - 1] : -1);
+    Group g{-1, 0};
+    if (r >= 0 && r != prev) {
+      long long lo = c + 1, hi = nchunks;  // first chunk after c whose first row exceeds r
+      while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (row0[mid] > r)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      g = Group{r, lo - (c + 1)};
+    }
+    groups[e] = g;
+  }
+}
+
+// A wave-uniform 64-bit value moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 struct ReuseArgs {
   const void* sv;
   const void* sidx;
-  const int32_t* rowid;
-  Carry* carry;
+  const unsigned long long* heads;
+  const long long* row0;
+  const Group* groups;
+  double* carry;
   const void* v;
   void* out;
   long long nnz;
   long long nchunks;
+  long long vlen;
   int out_f64;
 };
 
@@ -94,141 +162,146 @@ __device__ __forceinline__ void put(const ReuseArgs& A, long long row, double x)
     to_global(static_cast<float*>(A.out))[row] = (float)x;
 }
 
-// One chunk per block: products, heads and ends of runs of equal row, the
+// One chunk of one wave: products, heads and ends of runs of equal row, the
 // segmented sums; rows inside the chunk are written, its first and last
-// rows' partial sums go to the carries.
-template <typename IdxT, int F>
-__global__ __launch_bounds__(kReuseThreads) void k_reuse_apply(ReuseArgs A) {
+// rows' partial sums go to the carries.  The chunk's first position always
+// opens a run here (its row may continue from the previous chunk).  `vp`
+// points to v in global memory or in LDS.
+template <typename SIdx, int F, typename VP>
+__device__ __forceinline__ void apply_chunk(const ReuseArgs& A, long long c, VP vp) {
   using FO = FormOps<F>;
   using Acc = typename FO::Acc;
   using In = typename FO::In;
-  constexpr int NT = kReuseThreads, IPT = kReuseIPT, NW = NT / 64;
-  __shared__ unsigned wsum[NW];
-  __shared__ Seg<F> wagg[NW];
-  const int tid = threadIdx.x, w = tid >> 6;
+  constexpr int IPT = kReuseIPT;
   const unsigned ln = lane_id();
   const gptr<const In> sv = to_global(static_cast<const In*>(A.sv));
-  const gptr<const IdxT> sidx = to_global(static_cast<const IdxT*>(A.sidx));
-  const gptr<const int32_t> rowid = to_global(A.rowid);
-  const gptr<const In> v = to_global(static_cast<const In*>(A.v));
-  for (long long b = blockIdx.x; b < A.nchunks; b += gridDim.x) {
-    const long long k0 = b * kReuseChunk;
-    const int n = (int)std::min<long long>(kReuseChunk, A.nnz - k0);
-    const int pw = w * 64 * IPT;  // wave w: positions [pw, pw + 64*IPT), rounds of 64
-    int row[IPT];
-    bool hd[IPT], end[IPT];
-    Acc prod[IPT];
-    {
-      int rprev[IPT], rnext[IPT];
-      In a[IPT];
-      IdxT ix[IPT];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const int p = pw + j * 64 + (int)ln;
-        const bool ok = p < n;
-        row[j] = ok ? rowid[k0 + p] : -1;
-        rprev[j] = (ok && p > 0) ? rowid[k0 + p - 1] : -1;
-        rnext[j] = (ok && p + 1 < n) ? rowid[k0 + p + 1] : -1;
-        a[j] = ok ? sv[k0 + p] : (In)0;
-        ix[j] = ok ? sidx[k0 + p] : (IdxT)0;
-      }
-      In g[IPT];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) g[j] = (pw + j * 64 + (int)ln < n) ? v[ix[j]] : (In)0;
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const int p = pw + j * 64 + (int)ln;
-        hd[j] = p < n && (p == 0 || row[j] != rprev[j]);
-        end[j] = p < n && (p == n - 1 || row[j] != rnext[j]);
-        prod[j] = FO::from_pay(FO::mul_prod(FO::start_prod(a[j]), g[j]));
-      }
-    }
-    // segmented scan in rounds of 64 consecutive positions, then across waves
-    uint64_t hm[IPT];
-    Acc val[IPT];
-    unsigned whc = 0;
-    {
-      Acc c = FO::zero();
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        hm[j] = ballot(hd[j]);
-        whc += (unsigned)__popcll(hm[j]);
-        Seg<F> e;
-        e.f = hd[j] ? 1 : 0;
-        e.v = (pw + j * 64 + (int)ln < n) ? prod[j] : FO::zero();
-        e = wave_seg_scan<F>(e);
-        val[j] = e.f ? e.v : FO::add(c, e.v);
-        c = FO::shfl_last(val[j]);
-      }
-      if (ln == 0) {
-        wsum[w] = whc;
-        wagg[w].f = whc ? 1 : 0;
-        wagg[w].v = c;
-      }
-    }
-    __syncthreads();
-    Seg<F> cw;
-    cw.f = 0;
-    cw.v = FO::zero();
-    unsigned hbw = 0;
-    for (int q = 0; q < w; ++q) {
-      cw = seg_combine<F>(cw, wagg[q]);
-      hbw += wsum[q];
-    }
-    {
-      bool lead = true;
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const uint64_t upto = hm[j] & (~0ull >> (63 - ln));
-        if (lead && upto == 0) val[j] = FO::add(cw.v, val[j]);
-        lead = lead && hm[j] == 0;
-      }
-    }
-    // run ends: the chunk's first run (one head so far) and last run (ending
-    // at the chunk's end) may continue in the neighbouring chunks
-    unsigned hrun = hbw;
+  const gptr<const SIdx> sidx = to_global(static_cast<const SIdx*>(A.sidx));
+  const long long k0 = c * kReuseChunk;
+  const int n = (int)std::min<long long>(kReuseChunk, A.nnz - k0);
+  uint64_t hm[IPT];  // run heads of every round of 64 positions
+  bool end[IPT];
+  Acc prod[IPT];
+  {
+    In a[IPT];
+    SIdx ix[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-      const int p = pw + j * 64 + (int)ln;
-      if (end[j]) {
-        const unsigned heads = hrun + (unsigned)__popcll(hm[j] & (~0ull >> (63 - ln)));
-        const bool firstrun = heads == 1, lastrun = p == n - 1;
-        const double x = FO::to_f64(val[j]);
-        if (!firstrun && !lastrun) {
-          put<F>(A, row[j], x);
-        } else {
-          Carry* cb = A.carry + 2 * b;
-          if (firstrun) cb[0] = Carry{row[j], x};
-          if (lastrun) cb[1] = firstrun ? Carry{-1, 0.0} : Carry{row[j], x};
-        }
-      }
-      hrun += (unsigned)__popcll(hm[j]);
+      const int p = j * 64 + (int)ln;
+      const bool ok = p < n;
+      a[j] = ok ? sv[k0 + p] : (In)0;
+      ix[j] = ok ? sidx[k0 + p] : (SIdx)0;
     }
-    __syncthreads();
+    uint64_t wd[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) wd[j] = uniform64(j * 64 < n ? A.heads[(k0 >> 6) + j] : 0ull);
+    In g[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) g[j] = (j * 64 + (int)ln < n) ? vp[ix[j]] : (In)0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int p = j * 64 + (int)ln;
+      const int rem = n - j * 64;  // positions of this round inside the chunk
+      const uint64_t vm = rem >= 64 ? ~0ull : (rem <= 0 ? 0ull : (~0ull >> (64 - rem)));
+      hm[j] = (wd[j] | (j == 0 ? 1ull : 0ull)) & vm;
+      // the last position of a round is followed by the next round's first
+      // (or ends the chunk)
+      const uint64_t nxt = ln < 63 ? (hm[j] >> (ln + 1)) : (j + 1 < IPT ? wd[j + 1] : 1ull);
+      end[j] = p < n && (p == n - 1 || (nxt & 1ull));
+      prod[j] = FO::from_pay(FO::mul_prod(FO::start_prod(a[j]), g[j]));
+    }
+  }
+  // segmented scan in rounds of 64 consecutive positions, the running sum of
+  // the open run carried from round to round; then the ends are written.
+  // A run's row is the chunk's first row plus the heads after the first.
+  const long long r0 = A.row0[c];
+  Acc run = FO::zero();
+  unsigned hrun = 0;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int p = j * 64 + (int)ln;
+    Seg<F> e;
+    e.f = (hm[j] >> ln) & 1ull ? 1 : 0;
+    e.v = p < n ? prod[j] : FO::zero();
+    e = wave_seg_scan<F>(e);
+    const Acc val = e.f ? e.v : FO::add(run, e.v);
+    run = FO::shfl_last(val);
+    if (end[j]) {
+      const unsigned heads = hrun + (unsigned)__popcll(hm[j] & (~0ull >> (63 - ln)));
+      const bool firstrun = heads == 1, lastrun = p == n - 1;
+      const double x = FO::to_f64(val);
+      if (!firstrun && !lastrun)
+        put<F>(A, r0 + (long long)heads - 1, x);
+      else if (firstrun)
+        to_global(A.carry)[2 * c] = x;
+      else
+        to_global(A.carry)[2 * c + 1] = x;
+    }
+    hrun += (unsigned)__popcll(hm[j]);
   }
 }
 
-// Rows that touch a chunk boundary: the entry holding a row's first partial
-// adds the following entries of the same row, in chunk order (FP64).
+// One chunk per wave, v gathered from global memory (no block-level
+// synchronisation).
+template <typename SIdx, int F>
+__global__ __launch_bounds__(kReuseThreads) void k_reuse_apply(ReuseArgs A) {
+  using In = typename FormOps<F>::In;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long c = (long long)blockIdx.x * (kReuseThreads / 64) + w;
+  if (c >= A.nchunks) return;  // the whole wave
+  apply_chunk<SIdx, F>(A, c, to_global(static_cast<const In*>(A.v)));
+}
+
+// v staged in LDS once per block (a gather from LDS instead of one cache
+// line per lane); the block's waves then loop over chunks.
+template <typename SIdx, int F>
+__global__ __launch_bounds__(kReuseLdsThreads) void k_reuse_apply_lds(ReuseArgs A) {
+  using In = typename FormOps<F>::In;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  In* vs = reinterpret_cast<In*>(smem);
+  const gptr<const In> gv = to_global(static_cast<const In*>(A.v));
+  for (long long i = threadIdx.x; i < A.vlen; i += kReuseLdsThreads) vs[i] = gv[i];
+  __syncthreads();
+  constexpr int NW = kReuseLdsThreads / 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (long long c = (long long)blockIdx.x * NW + w; c < A.nchunks; c += (long long)gridDim.x * NW)
+    apply_chunk<SIdx, F>(A, c, static_cast<const In*>(vs));
+}
+
+// Rows that touch a chunk boundary: the entry that opens a row adds the
+// group's following entries in a fixed order that depends only on the plan
+// (FP64): serially for up to kSerial entries, else the wave's 64 lanes sum
+// strided subsets serially and a butterfly adds them.
 template <int F>
 __global__ __launch_bounds__(256) void k_reuse_combine(ReuseArgs A) {
+  constexpr long long kSerial = 32;
   const long long E = 2 * A.nchunks;
-  const Carry* c = A.carry;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long r = c[e].row;
-    if (r < 0) continue;
-    long long q = e - 1;  // the previous used entry (at most one unused entry lies between)
-    while (q >= 0 && c[q].row < 0) --q;
-    if (q >= 0 && c[q].row == r) continue;  // not the row's first partial
-    double s = c[e].val;
-    for (long long f = e + 1; f < E; ++f) {
-      const long long rf = c[f].row;
-      if (rf < 0) continue;
-      if (rf != r) break;
-      s += c[f].val;
-    }
-    put<F>(A, r, s);
+  const gptr<const double> cv = to_global(static_cast<const double*>(A.carry));
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  Group g{-1, 0};
+  double s = 0.0;
+  if (e < E) {
+    g.row = to_global(A.groups)[e].row;
+    g.cnt = to_global(A.groups)[e].cnt;
+    if (g.row >= 0) s = cv[e];
+  }
+  const long long c1 = e >> 1;
+  if (g.row >= 0 && g.cnt <= kSerial) {
+#pragma unroll 8
+    for (long long k = 0; k < g.cnt; ++k) s += cv[2 * (c1 + 1 + k)];
+    put<F>(A, g.row, s);
+  }
+  // long rows: the whole wave sums each one
+  const unsigned ln = lane_id();
+  uint64_t todo = ballot(g.row >= 0 && g.cnt > kSerial);
+  while (todo) {
+    const int L = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const long long cL = __shfl(c1, L, 64), nL = __shfl(g.cnt, L, 64);
+    double part = 0.0;
+    for (long long k = ln; k < nL; k += 64) part += cv[2 * (cL + 1 + k)];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+    if ((int)ln == L) put<F>(A, g.row, s + part);
   }
 }
 
@@ -259,19 +332,25 @@ int ttv_reuse_plan_create(const ttv_coo_desc* X, int32_t mode, int32_t flags, tt
   p->out_f64 = (p->form == kF64 || (flags & TTV_OUT_F64)) ? 1 : 0;
   p->nnz = X->nnz;
   p->nchunks = (X->nnz + kReuseChunk - 1) / kReuseChunk;
-  const size_t isz = p->idx64 ? 8 : 4, vsz = p->form == kF64 ? 8 : 4;
+  p->sidx32 = X->shape[mode] <= (1LL << 32) ? 1 : 0;
+  const size_t isz = p->sidx32 ? 4 : 8, vsz = p->form == kF64 ? 8 : 4;
   size_t o = kReuseHdr;
   p->off_sv = o;
   o = align256(o + (size_t)p->nnz * vsz);
   p->off_sidx = o;
   o = align256(o + (size_t)p->nnz * isz);
-  p->off_rowid = o;
-  o = align256(o + (size_t)p->nnz * 4);
+  p->off_heads = o;
+  o = align256(o + (size_t)((p->nnz + 63) / 64) * 8);
+  p->off_row0 = o;
+  o = align256(o + (size_t)p->nchunks * 8);
+  p->off_groups = o;
+  o = align256(o + (size_t)(2 * p->nchunks) * sizeof(Group));
   p->off_carry = o;
-  o = align256(o + (size_t)(2 * p->nchunks) * sizeof(Carry));
+  o = align256(o + (size_t)(2 * p->nchunks) * sizeof(double));
   p->data_bytes = o;
   p->off_perm = align256(p->P.L.end);
-  p->setup_bytes = p->off_perm + align256((size_t)p->nnz * 4);
+  p->off_rowid = p->off_perm + align256((size_t)p->nnz * 4);
+  p->setup_bytes = p->off_rowid + align256((size_t)p->nnz * 4);
   *plan = p;
   return TTV_OK;
 }
@@ -297,7 +376,7 @@ int ttv_reuse_setup(ttv_reuse_plan* plan, void* data, size_t data_bytes, void* o
   PipePlan P = plan->P;
   P.d0.out_subs = out_subs;
   P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
-  P.d0.seg_out = reinterpret_cast<int32_t*>(d + plan->off_rowid);
+  P.d0.seg_out = reinterpret_cast<int32_t*>(w + plan->off_rowid);
   P.d0.perm_out = reinterpret_cast<int32_t*>(w + plan->off_perm);
   P.cus = device_cus();
   int rc = launch_pipeline(P, ws, s);
@@ -306,31 +385,43 @@ int ttv_reuse_setup(ttv_reuse_plan* plan, void* data, size_t data_bytes, void* o
   const long long sjm = (long long)plan->mode * X.stride_j;
   const int g = (int)std::min<long long>(std::max<long long>(1, (plan->nnz + 255) / 256), 8LL * P.cus);
   const int32_t* perm = P.d0.perm_out;
+  const int32_t* rowid = P.d0.seg_out;
   long long* hdr = reinterpret_cast<long long*>(d);
   const long long* onnz = reinterpret_cast<const long long*>(out_nnz);
-  if (plan->idx64) {
-    if (plan->form == kF64)
-      hipLaunchKernelGGL((k_reuse_gather<long long, double>), dim3(g), dim3(256), 0, s,
-                         static_cast<const long long*>(X.subs), X.stride_e, sjm, static_cast<const double*>(X.vals),
-                         perm, plan->nnz, reinterpret_cast<double*>(d + plan->off_sv),
-                         reinterpret_cast<long long*>(d + plan->off_sidx), onnz, hdr);
+  auto heads = reinterpret_cast<unsigned long long*>(d + plan->off_heads);
+  auto row0 = reinterpret_cast<long long*>(d + plan->off_row0);
+  auto run = [&](auto idx_tag, auto val_tag, auto sidx_tag) {
+    using IdxT = decltype(idx_tag);
+    using In = decltype(val_tag);
+    using SIdx = decltype(sidx_tag);
+    hipLaunchKernelGGL((k_reuse_gather<IdxT, In, SIdx>), dim3(g), dim3(256), 0, s, static_cast<const IdxT*>(X.subs),
+                       X.stride_e, sjm, static_cast<const In*>(X.vals), perm, rowid, plan->nnz,
+                       reinterpret_cast<In*>(d + plan->off_sv), reinterpret_cast<SIdx*>(d + plan->off_sidx), heads,
+                       row0, onnz, hdr);
+  };
+  auto by_sidx = [&](auto idx_tag, auto val_tag) {
+    if (plan->sidx32)
+      run(idx_tag, val_tag, (uint32_t)0);
     else
-      hipLaunchKernelGGL((k_reuse_gather<long long, float>), dim3(g), dim3(256), 0, s,
-                         static_cast<const long long*>(X.subs), X.stride_e, sjm, static_cast<const float*>(X.vals),
-                         perm, plan->nnz, reinterpret_cast<float*>(d + plan->off_sv),
-                         reinterpret_cast<long long*>(d + plan->off_sidx), onnz, hdr);
-  } else {
+      run(idx_tag, val_tag, (long long)0);
+  };
+  auto by_val = [&](auto idx_tag) {
     if (plan->form == kF64)
-      hipLaunchKernelGGL((k_reuse_gather<int, double>), dim3(g), dim3(256), 0, s, static_cast<const int*>(X.subs),
-                         X.stride_e, sjm, static_cast<const double*>(X.vals), perm, plan->nnz,
-                         reinterpret_cast<double*>(d + plan->off_sv), reinterpret_cast<int*>(d + plan->off_sidx),
-                         onnz, hdr);
+      by_sidx(idx_tag, 0.0);
     else
-      hipLaunchKernelGGL((k_reuse_gather<int, float>), dim3(g), dim3(256), 0, s, static_cast<const int*>(X.subs),
-                         X.stride_e, sjm, static_cast<const float*>(X.vals), perm, plan->nnz,
-                         reinterpret_cast<float*>(d + plan->off_sv), reinterpret_cast<int*>(d + plan->off_sidx),
-                         onnz, hdr);
+      by_sidx(idx_tag, 0.0f);
+  };
+  if (plan->idx64)
+    by_val((long long)0);
+  else
+    by_val((int)0);
+  if (plan->nnz > 0) {
+    const long long ge = std::min<long long>((2 * plan->nchunks + 255) / 256, 4LL * P.cus);
+    hipLaunchKernelGGL(k_reuse_groups, dim3((unsigned)ge), dim3(256), 0, s, rowid,
+                       static_cast<const long long*>(row0), plan->nnz, plan->nchunks,
+                       reinterpret_cast<Group*>(d + plan->off_groups));
   }
+  plan->cus = P.cus;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_last_hip_error((int)e);
@@ -353,32 +444,54 @@ int ttv_reuse_apply(const ttv_reuse_plan* plan, const void* v, int64_t v_len, vo
   ReuseArgs A;
   A.sv = d + plan->off_sv;
   A.sidx = d + plan->off_sidx;
-  A.rowid = reinterpret_cast<const int32_t*>(d + plan->off_rowid);
-  A.carry = reinterpret_cast<Carry*>(d + plan->off_carry);
+  A.heads = reinterpret_cast<const unsigned long long*>(d + plan->off_heads);
+  A.row0 = reinterpret_cast<const long long*>(d + plan->off_row0);
+  A.groups = reinterpret_cast<const Group*>(d + plan->off_groups);
+  A.carry = reinterpret_cast<double*>(d + plan->off_carry);
   A.v = v;
   A.out = out_vals;
   A.nnz = plan->nnz;
   A.nchunks = plan->nchunks;
   A.out_f64 = plan->out_f64;
-  const int ga = (int)std::min<long long>(plan->nchunks, 1LL << 20);
-  const int gc = (int)std::min<long long>(std::max<long long>(1, (2 * plan->nchunks + 255) / 256), 1024);
+  A.vlen = v_len;
+  // v is staged in LDS when it fits and the blocks' copies of it (from L2)
+  // cost fewer bytes than the values they gather for
+  const size_t vbytes = (size_t)v_len * (plan->form == kF64 ? 8 : 4);
+  const size_t lds = align256(vbytes);
+  const long long per_cu = lds <= 80 * 1024 ? 2 : 1;
+  const long long gl = std::min<long long>(per_cu * plan->cus,
+                                           (plan->nchunks + kReuseLdsThreads / 64 - 1) / (kReuseLdsThreads / 64));
+  const bool use_lds = lds <= kReuseMaxVLds && (size_t)gl * vbytes <= (size_t)plan->nnz * (vbytes / v_len);
+  const long long ga = (plan->nchunks + kReuseThreads / 64 - 1) / (kReuseThreads / 64);
+  const long long gc = (2 * plan->nchunks + 255) / 256;
+  auto launch = [&](auto sidx_tag, auto form_tag) {
+    using SIdx = decltype(sidx_tag);
+    constexpr int F = decltype(form_tag)::value;
+    if (use_lds) {
+      hipFuncSetAttribute((const void*)k_reuse_apply_lds<SIdx, F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+      hipLaunchKernelGGL((k_reuse_apply_lds<SIdx, F>), dim3((unsigned)gl), dim3(kReuseLdsThreads), lds, s, A);
+    } else {
+      hipLaunchKernelGGL((k_reuse_apply<SIdx, F>), dim3((unsigned)ga), dim3(kReuseThreads), 0, s, A);
+    }
+  };
   prof_begin(TTV_PROF_REUSE, s);
   if (plan->form == kF64) {
-    if (plan->idx64)
-      hipLaunchKernelGGL((k_reuse_apply<long long, kF64>), dim3(ga), dim3(kReuseThreads), 0, s, A);
+    if (plan->sidx32)
+      launch((uint32_t)0, std::integral_constant<int, kF64>());
     else
-      hipLaunchKernelGGL((k_reuse_apply<int, kF64>), dim3(ga), dim3(kReuseThreads), 0, s, A);
+      launch((long long)0, std::integral_constant<int, kF64>());
   } else {
-    if (plan->idx64)
-      hipLaunchKernelGGL((k_reuse_apply<long long, kC32>), dim3(ga), dim3(kReuseThreads), 0, s, A);
+    if (plan->sidx32)
+      launch((uint32_t)0, std::integral_constant<int, kC32>());
     else
-      hipLaunchKernelGGL((k_reuse_apply<int, kC32>), dim3(ga), dim3(kReuseThreads), 0, s, A);
+      launch((long long)0, std::integral_constant<int, kC32>());
   }
   prof_end(TTV_PROF_REUSE, s);
   if (plan->form == kF64)
-    hipLaunchKernelGGL(k_reuse_combine<kF64>, dim3(gc), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_reuse_combine<kF64>, dim3((unsigned)gc), dim3(256), 0, s, A);
   else
-    hipLaunchKernelGGL(k_reuse_combine<kC32>, dim3(gc), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_reuse_combine<kC32>, dim3((unsigned)gc), dim3(256), 0, s, A);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_last_hip_error((int)e);

@@ -127,11 +127,14 @@ def test_reuse_plan_host_checks():
     try:
         nd, nw = ctypes.c_size_t(0), ctypes.c_size_t(0)
         assert lib.ttv_reuse_sizes(plan, ctypes.byref(nd), ctypes.byref(nw)) == 0
-        # values, contracted indices and output rows of every nonzero, plus per-chunk carries
-        assert nnz * (8 + 8 + 4) <= nd.value <= nnz * (8 + 8 + 4) + 2 * 16 * (nnz // 4096 + 1) + 4096
+        # values, 32-bit contracted indices and a row-start bit of every nonzero, plus
+        # each 512-position chunk's first row, two carry groups and two carries
+        chunks = nnz // 512 + 1
+        base = nnz * 8 + nnz * 4 + nnz // 8
+        assert base <= nd.value <= base + chunks * (8 + 2 * 16 + 2 * 8) + 7 * 256
         ws_pipe = ctypes.c_size_t(0)
         assert lib.ttv_coo_workspace(ctypes.byref(d), 1, 0, ctypes.byref(ws_pipe)) == 0
-        assert nw.value >= ws_pipe.value + 4 * nnz  # the pipeline, then the permutation
+        assert nw.value >= ws_pipe.value + 8 * nnz  # the pipeline, then the permutation and rows
         v = ctypes.c_void_p(1)
         # apply before setup; setup with buffers too small: rejected before anything is enqueued
         assert lib.ttv_reuse_apply(plan, v, 10_000, v, None) == E["ARG"]

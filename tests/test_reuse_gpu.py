@@ -79,8 +79,8 @@ def test_compensated_fp32_skewed():
 
 
 def test_rows_spanning_chunks():
-    """One output row holds 20000 nonzeros (a single-key bucket over several
-    4096-position chunks); small rows sit on both sides of it."""
+    """One output row holds 20000 nonzeros (a single-key bucket over many
+    chunks); small rows sit on both sides of it."""
     P = _api()
     rng = np.random.default_rng(11)
     shape = (7, 50, 9)
@@ -95,6 +95,50 @@ def test_rows_spanning_chunks():
     v = rng.uniform(0.5, 1.5, 50)
     gs, gv = _apply(R, v)
     check_ttv(X, 1, v, gs, gv, F64_TOL, "reuse heavy row")
+
+
+def test_rows_of_many_lengths():
+    """Rows of 600 to 100000 nonzeros next to each other and between small
+    rows: the partial sums of rows crossing chunk boundaries are combined by
+    one lane (short rows) or by a whole wave (long rows)."""
+    P = _api()
+    rng = np.random.default_rng(12)
+    shape = (40, 30, 9)
+    parts = []
+    for i, n in enumerate([600, 16000, 17500, 3, 100000, 1, 40000]):
+        parts.append(np.column_stack([np.full(n, 2 * i + 1), rng.integers(0, 30, n), np.full(n, i)]))
+        m = int(rng.integers(0, 700))
+        parts.append(np.column_stack([np.full(m, 2 * i + 2), rng.integers(0, 30, m), rng.integers(0, 9, m)]))
+    subs_np = np.vstack(parts).astype(np.int32)
+    subs_np = subs_np[rng.permutation(subs_np.shape[0])]
+    vals_np = rng.standard_normal(subs_np.shape[0])
+    X = synth.COO(subs_np, vals_np, shape)
+    subs, vals = to_gpu(X)
+    say("reuse rows of many lengths")
+    R = P.ReuseTTV(subs, vals, shape, 1)
+    for k in range(2):
+        v = rng.standard_normal(30)
+        gs, gv = _apply(R, v)
+        check_ttv(X, 1, v, gs, gv, F64_TOL, f"reuse many lengths vector {k}")
+
+
+@pytest.mark.parametrize("n_mode,dtype", [(40000, np.float64), (20000, np.float32)])
+def test_vector_too_long_for_lds(n_mode, dtype):
+    """A contracted mode of 40000 (FP64) or 20000 (FP32) entries: above the
+    vector size that is staged in LDS (or not worth staging at this nnz), so
+    the apply gathers v from global memory."""
+    P = _api()
+    rng = np.random.default_rng(n_mode)
+    shape = (60, n_mode, 50)
+    nnz = 300_000
+    subs_np = np.column_stack([rng.integers(0, s, nnz) for s in shape]).astype(np.int64)
+    X = synth.COO(subs_np, rng.uniform(0.0, 1.0, nnz).astype(dtype), shape)
+    subs, vals = to_gpu(X)
+    say(f"reuse global gather {n_mode} {np.dtype(dtype).name}")
+    R = P.ReuseTTV(subs, vals, shape, 1, out_f64=True)
+    v = rng.uniform(0.0, 1.0, n_mode).astype(dtype)
+    gs, gv = _apply(R, v)
+    check_ttv(X, 1, v, gs, gv, F64_TOL if dtype == np.float64 else C32_TOL, f"reuse global gather {n_mode}")
 
 
 @pytest.mark.parametrize("nnz", [0, 1, 4097])
