@@ -133,6 +133,7 @@ def reuse_comparison(X, subs, vals, v, K, ttv_us):
     return {"mode": 0, "setup_ms": setup_ms, "ms_per_apply": apply_ms, "nnz_per_s": nnz / (apply_ms * 1e-3),
             "speedup_vs_ttv": ttv_us / (apply_ms * 1e3), "max_rel_err_sampled": err,
             "kernel": {"name": "k_reuse_apply", "avg_launch_us": kern_ms * 1e3, "alg_bytes_per_launch": alg,
+                       "traffic": kernel_traffic("k_reuse_apply", "uniform1e7"),
                        "achieved": alg / (kern_ms * 1e-3) / 1e9, "frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
