@@ -12,6 +12,12 @@ from .ttv_oracle import (  # noqa: F401
     allbut_abs,
     allbut_products,
     allbut_vjp,
+    dense_wanted,
+    densify,
+    drop_zeros,
+    full,
+    full_abs,
+    full_products,
     products,
     regression_grad,
     regression_loss,

@@ -237,6 +237,61 @@ def allbut_abs(subs, vals, shape, keep, vecs) -> np.ndarray:
     return out
 
 
+def full_products(subs, vals, vecs) -> np.ndarray:
+    """Per nonzero: a_e times x_j[i_j(e)] for every mode j, multiplied left to
+    right in ascending mode order, in FP64."""
+    subs = np.asarray(subs)
+    p = np.asarray(vals, dtype=np.float64).copy()
+    for j in range(subs.shape[1]):
+        p = p * np.asarray(vecs[j], dtype=np.float64)[subs[:, j]]
+    return p
+
+
+def full(subs, vals, shape, vecs) -> float:
+    """Product with a vector in every mode (n_v = d in Sec. 3.3): the scalar
+    sum over the stored nonzeros of a_e times x_j[i_j(e)] for every mode j.
+    For d = 1 this is the dot product of a sparse and a dense vector
+    (Sec. 3.1).  Correctly rounded (fsum); 0 for nnz = 0."""
+    subs = np.asarray(subs)
+    d, nnz = _check(subs, vals, shape)
+    if d < 1:
+        raise OracleError("order must be at least 1")
+    for j in range(d):
+        if np.asarray(vecs[j]).shape != (int(shape[j]),):
+            raise OracleError(f"vector {j} has the wrong length")
+    return math.fsum(full_products(subs, vals, vecs).tolist())
+
+
+def full_abs(subs, vals, shape, vecs) -> float:
+    """fsum of |products| of ``full`` (its condition scale)."""
+    return math.fsum(np.abs(full_products(np.asarray(subs), vals, vecs)).tolist())
+
+
+def drop_zeros(newsubs, newvals):
+    """The `nonzero` step of the pyttb procedure (Sec. 3.3) as an option:
+    output entries whose sum is exactly zero are removed, the rest keep
+    their order."""
+    keep = np.asarray(newvals) != 0.0
+    return np.asarray(newsubs)[keep], np.asarray(newvals)[keep]
+
+
+def dense_wanted(nnz_out: int, newshape) -> bool:
+    """The dense-conversion test of the pyttb procedure (Sec. 3.3): more than
+    half of the result's cells are stored, i.e. 2 * nnz_out > prod(newshape)
+    (integer arithmetic)."""
+    return 2 * int(nnz_out) > math.prod(int(s) for s in newshape)
+
+
+def densify(newsubs, newvals, newshape) -> np.ndarray:
+    """Dense array of a sparse result: the stored values at their tuples,
+    zero elsewhere."""
+    out = np.zeros(tuple(int(s) for s in newshape), dtype=np.float64)
+    ns = np.asarray(newsubs)
+    if ns.shape[0]:
+        out[tuple(ns.T)] = np.asarray(newvals, dtype=np.float64)
+    return out
+
+
 def _segment_of(subs, shape, mode, newsubs) -> np.ndarray:
     """Output row of each nonzero: where its remaining-mode tuple sits in newsubs."""
     subs = np.asarray(subs)

@@ -387,3 +387,127 @@ def test_golden_fixtures_still_match():
     vecs = [np.array(w) for w in g["vecs"]]
     for k in g["keeps"]:
         assert oracle.allbut(subs, vals, shape, k["keep"], vecs).tolist() == k["y"]
+
+
+# --------------------------------------------------------------------------
+# Product with a vector in every mode (n_v = d, Sec. 3.3; d = 1 is the
+# sparse-dense dot product of Sec. 3.1).
+# --------------------------------------------------------------------------
+def test_full_hand_example():
+    # x0 = (10, 100), x1 = (1, 2), x2 = (3, 7):
+    #   a_000: 1*10*1*3 = 30     a_010: 2*10*2*3 = 120    a_101: 3*100*1*7 = 2100
+    #   a_111: 4*100*2*7 = 5600  a_001: 5*10*1*7 = 350    total 8200
+    vecs = [np.array([10.0, 100.0]), np.array([1.0, 2.0]), np.array([3.0, 7.0])]
+    assert oracle.full(HAND_SUBS, HAND_VALS, (2, 2, 2), vecs) == 8200.0
+    assert oracle.full_abs(HAND_SUBS, -HAND_VALS, (2, 2, 2), vecs) == 8200.0
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
+def test_full_dense_brute_force(d):
+    rng = np.random.default_rng(40 + d)
+    shape = tuple(int(s) for s in rng.integers(2, 7, d))
+    nnz = 60
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    X = synth.COO(subs, rng.standard_normal(nnz), shape)
+    vecs = [rng.standard_normal(s) for s in shape]
+    D = dense_of(X)
+    for j in range(d):  # contract mode 0 each time (the next original mode)
+        D = np.tensordot(vecs[j], D, axes=([0], [0]))
+    got = oracle.full(X.subs, X.vals, shape, vecs)
+    assert abs(got - float(D)) <= 1e-13 * oracle.full_abs(X.subs, X.vals, shape, vecs)
+
+
+def test_full_order_one_is_the_dot_product():
+    rng = np.random.default_rng(7)
+    n = 500
+    idx = rng.choice(n, 120, replace=False)
+    a = rng.integers(-50, 50, 120).astype(np.float64)
+    x = rng.integers(-50, 50, n).astype(np.float64)
+    dense = np.zeros(n)
+    dense[idx] = a
+    want = sum(int(p) * int(q) for p, q in zip(dense.astype(np.int64), x.astype(np.int64)))
+    assert oracle.full(idx[:, None], a, (n,), [x]) == float(want)
+    assert oracle.full(idx[:, None], a, (n,), [x]) == float(np.dot(dense, x))
+
+
+@pytest.mark.parametrize("d,seed", [(3, 0), (4, 1), (5, 2)])
+def test_full_integer_exact(d, seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(s) for s in rng.integers(3, 9, d))
+    nnz = 400
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    vals = rng.integers(-9, 10, nnz)
+    vecs = [rng.integers(-9, 10, s) for s in shape]
+    want = 0
+    for e in range(nnz):
+        t = int(vals[e])
+        for j in range(d):
+            t *= int(vecs[j][subs[e, j]])
+        want += t
+    got = oracle.full(subs, vals.astype(np.float64), shape, [v.astype(np.float64) for v in vecs])
+    assert got == float(want)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_full_is_allbut_dotted_with_the_last_vector(d):
+    rng = np.random.default_rng(90 + d)
+    shape = tuple(int(s) for s in rng.integers(3, 12, d))
+    nnz = 300
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    vals = rng.uniform(0.0, 1.0, nnz)
+    vecs = [rng.uniform(0.0, 1.0, s) for s in shape]
+    got = oracle.full(subs, vals, shape, vecs)
+    for keep in range(d):
+        y = oracle.allbut(subs, vals, shape, keep, vecs)
+        assert abs(got - math.fsum((y * vecs[keep]).tolist())) <= 1e-13 * got
+
+
+def test_full_empty_is_zero():
+    assert oracle.full(np.zeros((0, 3), dtype=np.int64), np.zeros(0), (4, 5, 6),
+                       [np.ones(4), np.ones(5), np.ones(6)]) == 0.0
+
+
+# --------------------------------------------------------------------------
+# pyttb-parity options of Sec. 3.3: the `nonzero` step (drop exact-zero sums)
+# and the dense conversion of results with more than half of the cells set.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_drop_zeros_integer_cancellation(mode):
+    rng = np.random.default_rng(mode)
+    shape = (6, 5, 4)
+    nnz = 300
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    vals = rng.choice([-1.0, 1.0], nnz)
+    v = np.ones(shape[mode])
+    sums = {}
+    R = [j for j in range(3) if j != mode]
+    for e in range(nnz):
+        k = tuple(int(subs[e, j]) for j in R)
+        sums[k] = sums.get(k, 0) + int(vals[e])
+    want = sorted(k for k, t in sums.items() if t != 0)
+    assert len(want) < len(sums)  # some sums cancel
+    ns, nv, _ = oracle.ttv(subs, vals, shape, mode, v)
+    ks, kv = oracle.drop_zeros(ns, nv)
+    assert [tuple(r) for r in ks.tolist()] == want
+    assert kv.tolist() == [float(sums[k]) for k in want]
+
+
+def test_dense_wanted_threshold():
+    assert not oracle.dense_wanted(5, (2, 5))
+    assert oracle.dense_wanted(6, (2, 5))
+    assert not oracle.dense_wanted(4, (3, 3))
+    assert oracle.dense_wanted(5, (3, 3))
+    assert not oracle.dense_wanted(0, (1,))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_densify_is_the_dense_contraction(mode):
+    rng = np.random.default_rng(20 + mode)
+    shape = (4, 5, 3)
+    nnz = 50
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    X = synth.COO(subs, rng.integers(-5, 6, nnz).astype(np.float64), shape)
+    v = rng.integers(-5, 6, shape[mode]).astype(np.float64)
+    ns, nv, nshape = oracle.ttv(X.subs, X.vals, shape, mode, v)
+    want = np.tensordot(dense_of(X), v, axes=([mode], [0]))
+    assert np.array_equal(oracle.densify(ns, nv, nshape), want)
