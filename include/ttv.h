@@ -163,6 +163,23 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes,
                   void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Product with a vector in every mode (n_v = d, Sec. 3.3): the scalar
+ *   y = sum over nonzeros e of vals[e] * prod_j vecs[j][subs(e, j)]
+ * (factors multiplied in ascending mode order).  For d = 1 it is the dot
+ * product of a sparse and a dense vector (Sec. 3.1).  1 <= d <= TTV_MAX_ORDER;
+ * nnz = 0 gives 0.  The summation order is fixed by nnz alone (bitwise
+ * repeatable on any device): a fixed set of waves sums fixed tiles, then a
+ * fixed tree; FP64 sums, or for TTV_F32 exact FP32 product pairs with Dot2
+ * compensated sums per lane and FP64 from the wave sums on.
+ *   vecs, vec_lens  host arrays of d device pointers / lengths (= shape[j])
+ *   y        device scalar (FP64; FP32 for TTV_F32 unless TTV_OUT_F64)
+ *   ws       workspace of ttv_coo_full_workspace bytes (about 64 KiB)
+ * ---------------------------------------------------------------------- */
+int ttv_coo_full_workspace(const ttv_coo_desc* X, int32_t flags, size_t* bytes);
+int ttv_coo_full(const ttv_coo_desc* X, const void* const* vecs, const int64_t* vec_lens, void* y,
+                 void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * All-but-one product (n_v = d - 1, Sec. 3.3): a dense vector
  *   y[i] = sum over nonzeros e with subs(e, keep) = i of
  *          vals[e] * prod_{j != keep} vecs[j][subs(e, j)]
@@ -275,7 +292,8 @@ void ttv_reuse_plan_destroy(ttv_reuse_plan* plan);
  * kernel: TTV_PROF_NONE disables; TTV_PROF_FINISH the leaf sort-reduce-write
  * kernel; TTV_PROF_SCATTER1 the first-level bucket scatter; TTV_PROF_HIST1
  * its histogram; TTV_PROF_DENSE the dense accumulation kernel;
- * TTV_PROF_REUSE the streaming kernel of ttv_reuse_apply.  Not thread-safe;
+ * TTV_PROF_REUSE the streaming kernel of ttv_reuse_apply; TTV_PROF_FULL the
+ * streaming kernel of ttv_coo_full.  Not thread-safe;
  * for measurement only.  ttv_profile_count returns k.
  */
 enum {
@@ -284,7 +302,8 @@ enum {
   TTV_PROF_SCATTER1 = 2,
   TTV_PROF_HIST1 = 3,
   TTV_PROF_DENSE = 4,
-  TTV_PROF_REUSE = 5
+  TTV_PROF_REUSE = 5,
+  TTV_PROF_FULL = 6
 };
 int ttv_profile_events(int32_t kernel, void* const* starts, void* const* stops, int32_t capacity);
 int ttv_profile_count(void);

@@ -10,6 +10,7 @@ from . import _lib  # noqa: F401
 from .api import (  # noqa: F401
     AllButOp,
     BatchedTTV,
+    FullOp,
     ReuseTTV,
     TTVAllButFunction,
     TTVFunction,
@@ -19,8 +20,9 @@ from .api import (  # noqa: F401
     ttv,
     ttv_allbut,
     ttv_backward,
+    ttv_full,
     ttv_multi,
 )
 
-__all__ = ["AllButOp", "BatchedTTV", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc", "plan_query", "ttv",
-           "ttv_allbut", "ttv_backward", "ttv_multi"]
+__all__ = ["AllButOp", "BatchedTTV", "FullOp", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
+           "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi"]

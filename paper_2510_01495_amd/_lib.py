@@ -17,7 +17,7 @@ I32, I64 = 0, 1
 F32, F64 = 0, 1
 VALIDATE, OUT_F64 = 0x1, 0x2
 BWD_SPARSE, BWD_ALLBUT = 0, 1
-PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE, PROF_REUSE = 0, 1, 2, 3, 4, 5
+PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE, PROF_REUSE, PROF_FULL = 0, 1, 2, 3, 4, 5, 6
 
 
 class CooDesc(ctypes.Structure):
@@ -50,6 +50,9 @@ SIGNATURES = {
     "ttv_coo_multi": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_int32), POINTER(c_void_p),
                                 POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_int32, c_void_p]),
+    "ttv_coo_full_workspace": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_size_t)]),
+    "ttv_coo_full": (c_int32, [POINTER(CooDesc), POINTER(c_void_p), POINTER(c_int64), c_void_p, c_void_p,
+                               c_size_t, c_int32, c_void_p]),
     "ttv_coo_allbut_workspace": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_size_t)]),
     "ttv_coo_allbut": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_void_p), POINTER(c_int64), c_void_p,
                                  c_void_p, c_size_t, c_int32, c_void_p]),

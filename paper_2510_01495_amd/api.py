@@ -192,6 +192,46 @@ def ttv_allbut(subs, vals, shape, keep: int, vecs, *, flags: int = 0, out_f64: b
     return op.y
 
 
+class FullOp:
+    """Planned product with a vector in every mode (n_v = d, Sec. 3.3): the
+    scalar sum over the nonzeros of vals times every mode's vector entry,
+    written to the 0-d tensor ``y``."""
+
+    def __init__(self, subs, vals, shape, vecs, *, flags: int = 0, out_f64: bool = False):
+        self.lib = L.load()
+        self.subs, self.vals, self.shape = subs, vals, tuple(int(s) for s in shape)
+        self.vecs = [v.contiguous() for v in vecs]
+        if len(self.vecs) != len(self.shape):
+            raise ValueError("one vector per mode")
+        for v in self.vecs:
+            if v.dtype != vals.dtype:
+                raise TypeError("vectors must have the dtype of vals")
+        self.flags = flags | (L.OUT_F64 if out_f64 else 0)
+        self.desc = coo_desc(subs, vals, self.shape)
+        self.c_vecs, self.c_lens = _vec_arrays(self.vecs, len(self.shape))
+        nb = c_size_t(0)
+        L.check(self.lib.ttv_coo_full_workspace(byref(self.desc), self.flags, byref(nb)), "ttv_coo_full_workspace")
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=subs.device)
+        self.y = torch.empty((), dtype=_out_value_dtype(vals, out_f64), device=subs.device)
+
+    def launch(self):
+        rc = self.lib.ttv_coo_full(byref(self.desc), self.c_vecs, self.c_lens, self.y.data_ptr(),
+                                   self.ws.data_ptr(), self.ws.numel(), self.flags, _stream(self.subs.device))
+        L.check(rc, "ttv_coo_full")
+
+    def device_error(self) -> int:
+        return self.lib.ttv_check_device_error(self.ws.data_ptr(), _stream(self.subs.device))
+
+
+def ttv_full(subs, vals, shape, vecs, *, flags: int = 0, out_f64: bool = False):
+    """Product with a vector in every mode (n_v = d, Sec. 3.3): a 0-d tensor.
+    For d = 1 it is the dot product of a sparse and a dense vector
+    (Sec. 3.1)."""
+    op = FullOp(subs, vals, shape, vecs, flags=flags, out_f64=out_f64)
+    op.launch()
+    return op.y
+
+
 def ttv_backward(subs, vals, shape, kind: str, mode: int, vecs, grad_out, *, want_vecs=None,
                  want_vals: bool = True, flags: int = 0):
     """Adjoint of ``ttv`` (kind="sparse": grad_out has one value per output

@@ -144,3 +144,27 @@ def test_reuse_plan_host_checks():
     finally:
         lib.ttv_reuse_plan_destroy(plan)
     lib.ttv_reuse_plan_destroy(None)  # a null plan is ignored
+
+
+def test_full_contraction_host_checks():
+    """Product with a vector in every mode: argument checks and workspace
+    size, host only (d = 1 is accepted here, unlike the sparse products)."""
+    L, lib = _lib()
+    E = dict(NULL=-1, ORDER=-2, SHAPE=-4, WORKSPACE=-7)
+    nb = ctypes.c_size_t(0)
+    assert lib.ttv_coo_full_workspace(ctypes.byref(_desc((7,), 5)), 0, ctypes.byref(nb)) == 0
+    assert 65536 <= nb.value <= 65536 + 4096
+    d9 = _desc((3,) * 8, 5)
+    d9.order = 9
+    assert lib.ttv_coo_full_workspace(ctypes.byref(d9), 0, ctypes.byref(nb)) == E["ORDER"]
+    assert lib.ttv_coo_full_workspace(ctypes.byref(_desc((3, 0), 5)), 0, ctypes.byref(nb)) == E["SHAPE"]
+    d = _desc((5, 6), 10)
+    v = ctypes.c_void_p(1)
+    vecs = (ctypes.c_void_p * 2)(1, 1)
+    lens = (ctypes.c_int64 * 2)(5, 6)
+    assert lib.ttv_coo_full(ctypes.byref(d), vecs, lens, v, v, 16, 0, None) == E["WORKSPACE"]
+    bad = (ctypes.c_int64 * 2)(5, 7)
+    assert lib.ttv_coo_full(ctypes.byref(d), vecs, bad, v, v, nb.value, 0, None) == E["SHAPE"]
+    assert lib.ttv_coo_full(ctypes.byref(d), vecs, lens, None, v, nb.value, 0, None) == E["NULL"]
+    none = (ctypes.c_void_p * 2)(1, None)
+    assert lib.ttv_coo_full(ctypes.byref(d), none, lens, v, v, nb.value, 0, None) == E["NULL"]
