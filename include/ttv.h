@@ -71,6 +71,11 @@ enum {
 /* Flags. */
 #define TTV_VALIDATE 0x1 /* check every index on the device (async, see ttv_check_device_error) */
 #define TTV_OUT_F64 0x2  /* FP32 inputs: write FP64 result values instead of FP32 */
+#define TTV_DROP_ZEROS 0x4 /* ttv_coo / ttv_coo_multi: remove output rows whose value is exactly 0
+                              (the nonzero step of the pyttb procedure, Sec. 3.3); the test is
+                              taken on the written value (FP64, or FP32 for FP32 output) and the
+                              remaining rows keep their order.  Needs a larger workspace (query
+                              with the flag).  Other entry points reject it (TTV_E_ARG). */
 
 /*
  * A COO sparse tensor (Sec. 3.3).  `subs` element (e, j) -- the mode-j index
@@ -161,6 +166,24 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes,
                   const void* const* vecs, const int64_t* vec_lens,
                   void* out_subs, void* out_vals, int64_t* out_nnz,
                   void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Dense form of a sparse result: the dense conversion of the pyttb procedure
+ * (Sec. 3.3), taken when more than half of the result's cells are stored.
+ * On the device: if 2 * (*nnz) > prod(shape) and dense_cap >= prod(shape),
+ * dense[row-major cell of row r's tuple] = vals[r] for r < *nnz, 0 in every
+ * other cell, and *is_dense = 1; otherwise dense is not touched and
+ * *is_dense = 0.  No host synchronisation.
+ *   order, shape     the result's order (1..TTV_MAX_ORDER) and dimensions
+ *   subs, vals, nnz  a sparse result as ttv_coo writes it (device; rows
+ *                    distinct, row-major subs of index_dtype, vals of
+ *                    value_dtype, device int64 count)
+ *   dense            device, dense_cap values of value_dtype (null if 0)
+ *   is_dense         device int32
+ * ---------------------------------------------------------------------- */
+int ttv_result_densify(int32_t order, const int64_t* shape, int32_t index_dtype, int32_t value_dtype,
+                       const void* subs, const void* vals, const int64_t* nnz, void* dense,
+                       int64_t dense_cap, int32_t* is_dense, ttv_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Product with a vector in every mode (n_v = d, Sec. 3.3): the scalar

@@ -22,7 +22,8 @@ from .api import (  # noqa: F401
     ttv_backward,
     ttv_full,
     ttv_multi,
+    ttv_pyttb,
 )
 
 __all__ = ["AllButOp", "BatchedTTV", "FullOp", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
-           "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi"]
+           "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]

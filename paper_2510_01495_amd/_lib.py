@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libttv.so")
 MAX_ORDER = 8
 I32, I64 = 0, 1
 F32, F64 = 0, 1
-VALIDATE, OUT_F64 = 0x1, 0x2
+VALIDATE, OUT_F64, DROP_ZEROS = 0x1, 0x2, 0x4
 BWD_SPARSE, BWD_ALLBUT = 0, 1
 PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE, PROF_REUSE, PROF_FULL = 0, 1, 2, 3, 4, 5, 6
 
@@ -50,6 +50,8 @@ SIGNATURES = {
     "ttv_coo_multi": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_int32), POINTER(c_void_p),
                                 POINTER(c_int64), c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_int32, c_void_p]),
+    "ttv_result_densify": (c_int32, [c_int32, POINTER(c_int64), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_int64, c_void_p, c_void_p]),
     "ttv_coo_full_workspace": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_size_t)]),
     "ttv_coo_full": (c_int32, [POINTER(CooDesc), POINTER(c_void_p), POINTER(c_int64), c_void_p, c_void_p,
                                c_size_t, c_int32, c_void_p]),

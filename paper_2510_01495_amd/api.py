@@ -4,6 +4,7 @@ step of the product runs in libttv.so's HIP kernels."""
 from __future__ import annotations
 
 import ctypes
+import math
 from ctypes import byref, c_int32, c_int64, c_size_t, c_void_p
 from typing import List, Optional, Sequence, Tuple
 
@@ -75,10 +76,13 @@ class TTVOp:
     outputs and workspace; ``launch()`` enqueues it on the current stream
     without synchronising, ``result()`` synchronises and slices."""
 
-    def __init__(self, subs, vals, shape, modes, vecs, *, flags: int = 0, out_f64: bool = False):
+    def __init__(self, subs, vals, shape, modes, vecs, *, flags: int = 0, out_f64: bool = False,
+                 drop_zeros: bool = False):
         self.lib = L.load()
         self.subs, self.vals, self.shape = subs, vals, tuple(int(s) for s in shape)
         self.modes = [int(m) for m in modes]
+        if drop_zeros:
+            flags |= L.DROP_ZEROS
         self.vecs = [v.contiguous() for v in vecs]
         for v in self.vecs:
             _check_tensor(v, "v")
@@ -126,6 +130,32 @@ def ttv(subs, vals, shape, mode: int, v, *, flags: int = 0, out_f64: bool = Fals
     """
     op = TTVOp(subs, vals, shape, [mode], [v], flags=flags, out_f64=out_f64)
     op.launch()
+    return op.result()
+
+
+def ttv_pyttb(subs, vals, shape, mode: int, v, *, out_f64: bool = False):
+    """The product as the pyttb procedure of Sec. 3.3 returns it: output
+    entries whose sum is exactly zero are removed, and a result with more
+    than half of its cells stored is returned as a dense tensor of the new
+    shape; otherwise (newsubs, newvals, newshape).  Both decisions are taken
+    on the device."""
+    op = TTVOp(subs, vals, shape, [mode], [v], out_f64=out_f64, drop_zeros=True)
+    op.launch()
+    cells = math.prod(op.newshape)
+    nnz = subs.shape[0]
+    cap = cells if cells < 2 * nnz else 0  # a dense result needs 2 * nnz_out > cells and nnz_out <= nnz
+    dev = subs.device
+    dense = torch.empty(max(cap, 1), dtype=op.out_vals.dtype, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    nd = len(op.newshape)
+    c_shape = (c_int64 * nd)(*op.newshape)
+    rc = op.lib.ttv_result_densify(nd, c_shape, _IDX[subs.dtype], _VAL[op.out_vals.dtype],
+                                   op.out_subs.data_ptr(), op.out_vals.data_ptr(), op.out_nnz.data_ptr(),
+                                   dense.data_ptr(), cap, flag.data_ptr(), _stream(dev))
+    L.check(rc, "ttv_result_densify")
+    if int(flag.item()):
+        L.check(op.device_error(), "device")
+        return dense[:cells].view(op.newshape)
     return op.result()
 
 

@@ -273,6 +273,11 @@ int ttv_plan_query(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, in
   return TTV_OK;
 }
 
+// Whether the product writes FP64 values (FP64 inputs, or TTV_OUT_F64).
+static int out_is_f64(const PipePlan& P, int flags) {
+  return (P.form == kF64 || (flags & TTV_OUT_F64)) ? 1 : 0;
+}
+
 int ttv_coo_multi_workspace(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, int32_t flags,
                             size_t* bytes) {
   if (!bytes) return TTV_E_NULL;
@@ -280,6 +285,8 @@ int ttv_coo_multi_workspace(const ttv_coo_desc* X, int32_t ncon, const int32_t* 
   const int rc = plan_single(X, ncon, modes, flags, kPipeTTV, P);
   if (rc) return rc;
   *bytes = P.L.end;
+  if (flags & TTV_DROP_ZEROS)
+    *bytes = ((P.L.end + 255) & ~(size_t)255) + drop_zeros_ws(X->nnz, P.d0.nrem, P.idx64, out_is_f64(P, flags));
   return TTV_OK;
 }
 
@@ -300,12 +307,35 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, con
     P.d0.vec[modes[c]] = vecs[c];
   }
   if (X->nnz > 0 && (!out_subs || !out_vals)) return TTV_E_NULL;
-  if (!ws || ws_bytes < P.L.end) return TTV_E_WORKSPACE;
-  P.d0.out_subs = out_subs;
-  P.d0.out_vals = out_vals;
-  P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
+  const bool drop = (flags & TTV_DROP_ZEROS) != 0;
+  const size_t tmp_off = (P.L.end + 255) & ~(size_t)255;
+  const int of64 = out_is_f64(P, flags);
+  const size_t need = drop ? tmp_off + drop_zeros_ws(X->nnz, P.d0.nrem, P.idx64, of64) : P.L.end;
+  if (!ws || ws_bytes < need) return TTV_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   P.cus = device_cus();
-  return launch_pipeline(P, ws, reinterpret_cast<hipStream_t>(stream));
+  if (!drop) {
+    P.d0.out_subs = out_subs;
+    P.d0.out_vals = out_vals;
+    P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
+    return launch_pipeline(P, ws, s);
+  }
+  // the product into the temporary area, then its rows with nonzero sums
+  long long *cnt, *counts;
+  void *tsubs, *tvals;
+  drop_zeros_layout(static_cast<char*>(ws) + tmp_off, X->nnz, P.d0.nrem, P.idx64, cnt, counts, tsubs, tvals);
+  P.d0.out_subs = tsubs;
+  P.d0.out_vals = tvals;
+  P.d0.out_nnz = cnt;
+  if (int rc2 = launch_pipeline(P, ws, s)) return rc2;
+  launch_drop_zeros(tsubs, tvals, cnt, counts, out_subs, out_vals, reinterpret_cast<long long*>(out_nnz),
+                    P.d0.nrem, P.idx64, of64, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  return TTV_OK;
 }
 
 int ttv_coo(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len, void* out_subs,

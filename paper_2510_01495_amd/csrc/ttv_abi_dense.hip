@@ -243,6 +243,7 @@ using namespace ttv;
 extern "C" {
 
 int ttv_coo_allbut_workspace(const ttv_coo_desc* X, int32_t keep, int32_t flags, size_t* bytes) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // sparse products only
   if (!bytes) return TTV_E_NULL;
   int form, idx64;
   int rc = check_common(X, keep, form, idx64);
@@ -256,6 +257,7 @@ int ttv_coo_allbut_workspace(const ttv_coo_desc* X, int32_t keep, int32_t flags,
 
 int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs, const int64_t* vec_lens, void* y,
                    void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // sparse products only
   int form, idx64;
   int rc = check_common(X, keep, form, idx64);
   if (rc) return rc;
@@ -297,6 +299,7 @@ int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
 
 int ttv_coo_backward_workspace(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, int32_t flags,
                                size_t* bytes) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // sparse products only
   if (!bytes) return TTV_E_NULL;
   int form, idx64;
   int rc = check_common(X, mode_or_keep, form, idx64);
@@ -323,6 +326,7 @@ int ttv_coo_backward_workspace(const ttv_coo_desc* X, int32_t kind, int32_t mode
 int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, const void* const* vecs,
                      const int64_t* vec_lens, const void* grad_out, void* const* grad_vecs, void* grad_vals,
                      void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // sparse products only
   int form, idx64;
   int rc = check_common(X, mode_or_keep, form, idx64);
   if (rc) return rc;

@@ -172,6 +172,7 @@ extern "C" {
 int ttv_batch_plan_create(int32_t count, const ttv_coo_desc* Xs, const int32_t* modes, const void* const* vs,
                           void* const* out_subs, void* const* out_vals, int64_t* out_nnz, int32_t flags,
                           const char* tune_cache, ttv_batch_plan** plan) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // not offered for batches
   if (!plan) return TTV_E_NULL;
   *plan = nullptr;
   if (count < 1) return TTV_E_ARG;

@@ -152,7 +152,7 @@ using namespace ttv;
 extern "C" {
 
 int ttv_coo_full_workspace(const ttv_coo_desc* X, int32_t flags, size_t* bytes) {
-  (void)flags;
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // sparse products only
   if (!bytes) return TTV_E_NULL;
   int form, idx64;
   if (int rc = check_full(X, form, idx64)) return rc;
@@ -162,6 +162,7 @@ int ttv_coo_full_workspace(const ttv_coo_desc* X, int32_t flags, size_t* bytes) 
 
 int ttv_coo_full(const ttv_coo_desc* X, const void* const* vecs, const int64_t* vec_lens, void* y, void* ws,
                  size_t ws_bytes, int32_t flags, ttv_stream_t stream) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // sparse products only
   int form, idx64;
   if (int rc = check_full(X, form, idx64)) return rc;
   if (!vecs || !vec_lens || !y) return TTV_E_NULL;

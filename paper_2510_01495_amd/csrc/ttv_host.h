@@ -43,6 +43,17 @@ int choose_r1(long long nnz, unsigned __int128 range, int bits);
 void prof_begin(int kernel, hipStream_t s);
 void prof_end(int kernel, hipStream_t s);
 
+// Removal of exact-zero sums from a sparse result (TTV_DROP_ZEROS): the
+// product writes into a temporary area laid out by drop_zeros_layout, then
+// launch_drop_zeros compacts the kept rows into the caller's output.
+constexpr int kDropBlocks = 512;
+size_t drop_zeros_ws(long long nnz, int nrem, int idx64, int out_f64);
+void drop_zeros_layout(void* tmp, long long nnz, int nrem, int idx64, long long*& cnt, long long*& counts,
+                       void*& subs, void*& vals);
+int launch_drop_zeros(const void* in_subs, const void* in_vals, const long long* in_nnz, long long* counts,
+                      void* out_subs, void* out_vals, long long* out_nnz, int nrem, int idx64, int out_f64,
+                      hipStream_t s);
+
 constexpr int kAssumedCUs = 256;  // MI355X; tiling never depends on the device queried at call time
 
 }  // namespace ttv

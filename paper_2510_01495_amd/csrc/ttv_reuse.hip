@@ -315,6 +315,7 @@ using namespace ttv;
 extern "C" {
 
 int ttv_reuse_plan_create(const ttv_coo_desc* X, int32_t mode, int32_t flags, ttv_reuse_plan** plan) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // a plan keeps every row (which sums vanish depends on v)
   if (!plan) return TTV_E_NULL;
   *plan = nullptr;
   ttv_reuse_plan* p = new (std::nothrow) ttv_reuse_plan();

@@ -168,3 +168,33 @@ def test_full_contraction_host_checks():
     assert lib.ttv_coo_full(ctypes.byref(d), vecs, lens, None, v, nb.value, 0, None) == E["NULL"]
     none = (ctypes.c_void_p * 2)(1, None)
     assert lib.ttv_coo_full(ctypes.byref(d), none, lens, v, v, nb.value, 0, None) == E["NULL"]
+
+
+def test_drop_zeros_flag_host_checks():
+    """TTV_DROP_ZEROS: a larger workspace for the sparse products; rejected by
+    the entry points whose results are not a sparse product's rows."""
+    L, lib = _lib()
+    d = _desc((100, 80, 60), 10_000)
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.ttv_coo_workspace(ctypes.byref(d), 1, 0, ctypes.byref(a)) == 0
+    assert lib.ttv_coo_workspace(ctypes.byref(d), 1, L.DROP_ZEROS, ctypes.byref(b)) == 0
+    # a second copy of the result (2 int64 indices + FP64 value per row) and the block counts
+    assert b.value >= a.value + 10_000 * 24 + 512 * 8
+    assert lib.ttv_coo_allbut_workspace(ctypes.byref(d), 0, L.DROP_ZEROS, ctypes.byref(a)) == -12
+    assert lib.ttv_coo_full_workspace(ctypes.byref(d), L.DROP_ZEROS, ctypes.byref(a)) == -12
+    plan = ctypes.c_void_p()
+    assert lib.ttv_reuse_plan_create(ctypes.byref(d), 1, L.DROP_ZEROS, ctypes.byref(plan)) == -12
+    assert not plan.value
+
+
+def test_densify_host_checks():
+    L, lib = _lib()
+    shape = (ctypes.c_int64 * 2)(3, 4)
+    v = ctypes.c_void_p(1)
+    assert lib.ttv_result_densify(0, shape, L.I64, L.F64, v, v, v, v, 12, v, None) == -2
+    assert lib.ttv_result_densify(2, shape, 7, L.F64, v, v, v, v, 12, v, None) == -5
+    assert lib.ttv_result_densify(2, shape, L.I64, L.F64, v, v, None, v, 12, v, None) == -1
+    assert lib.ttv_result_densify(2, shape, L.I64, L.F64, v, v, v, None, 12, v, None) == -1
+    assert lib.ttv_result_densify(2, shape, L.I64, L.F64, v, v, v, v, -1, v, None) == -12
+    bad = (ctypes.c_int64 * 2)(3, 0)
+    assert lib.ttv_result_densify(2, bad, L.I64, L.F64, v, v, v, v, 12, v, None) == -4
