@@ -18,6 +18,9 @@ from .ttv_oracle import (  # noqa: F401
     full,
     full_abs,
     full_products,
+    mttkrp,
+    mttkrp_abs,
+    mttkrp_products,
     products,
     regression_grad,
     regression_loss,

@@ -267,6 +267,62 @@ def full_abs(subs, vals, shape, vecs) -> float:
     return math.fsum(np.abs(full_products(np.asarray(subs), vals, vecs)).tolist())
 
 
+def mttkrp(subs, vals, shape, mode, factors) -> np.ndarray:
+    """Sparse MTTKRP, the matricized tensor times Khatri-Rao product that the
+    paper names as its next target (built on the same per-nonzero product as
+    Eq. 3): for every index i of ``mode`` and column r,
+
+        M[i, r] = sum over nonzeros e with subs(e, mode) = i of
+                  a_e * prod_{j != mode} U_j[subs(e, j), r],
+
+    the factors multiplied in ascending mode order.  ``factors`` holds one
+    (shape[j], R) matrix per mode (entry ``mode`` is ignored).  Returns the
+    dense (shape[mode], R) FP64 matrix; rows no nonzero reaches are 0.  Each
+    entry is an fsum (correctly rounded)."""
+    subs = np.asarray(subs)
+    d, nnz = _check(subs, vals, shape)
+    remaining_modes(d, mode)
+    R = None
+    for j in range(d):
+        if j == mode:
+            continue
+        U = np.asarray(factors[j])
+        if U.ndim != 2 or U.shape[0] != int(shape[j]):
+            raise OracleError(f"factor {j} must be (shape[{j}], R)")
+        if R is None:
+            R = U.shape[1]
+        elif U.shape[1] != R:
+            raise OracleError("every factor must have R columns")
+    P = mttkrp_products(subs, vals, mode, factors)
+    out = np.zeros((int(shape[mode]), R), dtype=np.float64)
+    order, starts = _group_rows(subs[:, [mode]].astype(np.int64))
+    Ps = P[order]
+    ks = subs[order, mode]
+    for g in range(starts.size - 1):
+        rows = Ps[starts[g]:starts[g + 1]]
+        out[int(ks[starts[g]])] = [math.fsum(rows[:, r].tolist()) for r in range(R)]
+    return out
+
+
+def mttkrp_products(subs, vals, mode, factors) -> np.ndarray:
+    """Per nonzero and column r: a_e times U_j[subs(e, j), r] for every mode
+    j != mode, multiplied left to right in ascending mode order (nnz, R)."""
+    subs = np.asarray(subs)
+    d = subs.shape[1]
+    P = np.asarray(vals, dtype=np.float64)[:, None].copy()
+    for j in range(d):
+        if j == mode:
+            continue
+        P = P * np.asarray(factors[j], dtype=np.float64)[subs[:, j]]
+    return P
+
+
+def mttkrp_abs(subs, vals, shape, mode, factors) -> np.ndarray:
+    """fsum of |products| per entry of ``mttkrp`` (its condition scale)."""
+    return mttkrp(subs, np.abs(np.asarray(vals, dtype=np.float64)), shape, mode,
+                  [None if f is None else np.abs(np.asarray(f, dtype=np.float64)) for f in factors])
+
+
 def drop_zeros(newsubs, newvals):
     """The `nonzero` step of the pyttb procedure (Sec. 3.3) as an option:
     output entries whose sum is exactly zero are removed, the rest keep

@@ -511,3 +511,79 @@ def test_densify_is_the_dense_contraction(mode):
     ns, nv, nshape = oracle.ttv(X.subs, X.vals, shape, mode, v)
     want = np.tensordot(dense_of(X), v, axes=([mode], [0]))
     assert np.array_equal(oracle.densify(ns, nv, nshape), want)
+
+
+# --------------------------------------------------------------------------
+# Sparse MTTKRP (the next kernel the paper names): M = X_(n) times the
+# Khatri-Rao product of the other factors.
+# --------------------------------------------------------------------------
+def _factors(rng, shape, R, mode, kind="normal"):
+    out = []
+    for j, s in enumerate(shape):
+        if j == mode:
+            out.append(None)
+        elif kind == "int":
+            out.append(rng.integers(-4, 5, (s, R)).astype(np.float64))
+        else:
+            out.append(rng.standard_normal((s, R)))
+    return out
+
+
+def test_mttkrp_hand_example():
+    # HAND tensor, mode 0, R = 2, U1 = [[1, 2], [3, 4]], U2 = [[5, 6], [7, 8]]
+    #   row 0: a_000*U1[0]*U2[0] + a_010*U1[1]*U2[0] + a_001*U1[0]*U2[1]
+    #        = (1*1*5 + 2*3*5 + 5*1*7, 1*2*6 + 2*4*6 + 5*2*8) = (70, 140)
+    #   row 1: a_101*U1[0]*U2[1] + a_111*U1[1]*U2[1] = (3*1*7 + 4*3*7, 3*2*8 + 4*4*8) = (105, 176)
+    U = [None, np.array([[1.0, 2.0], [3.0, 4.0]]), np.array([[5.0, 6.0], [7.0, 8.0]])]
+    M = oracle.mttkrp(HAND_SUBS, HAND_VALS, (2, 2, 2), 0, U)
+    assert M.tolist() == [[70.0, 140.0], [105.0, 176.0]]
+
+
+@pytest.mark.parametrize("d,mode", [(2, 0), (2, 1), (3, 0), (3, 1), (3, 2), (4, 2), (5, 4)])
+def test_mttkrp_dense_brute_force(d, mode):
+    rng = np.random.default_rng(10 * d + mode)
+    shape = tuple(int(s) for s in rng.integers(2, 7, d))
+    nnz, R = 80, 5
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    X = synth.COO(subs, rng.standard_normal(nnz), shape)
+    U = _factors(rng, shape, R, mode)
+    D = dense_of(X)
+    letters = "abcdefgh"[:d]
+    terms = [letters] + [letters[j] + "r" for j in range(d) if j != mode]
+    want = np.einsum(",".join(terms) + "->" + letters[mode] + "r", D, *[U[j] for j in range(d) if j != mode])
+    got = oracle.mttkrp(X.subs, X.vals, shape, mode, U)
+    scale = oracle.mttkrp_abs(X.subs, X.vals, shape, mode, U)
+    assert np.all(np.abs(got - want) <= 1e-13 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_mttkrp_columns_are_all_but_one_products(mode):
+    rng = np.random.default_rng(60 + mode)
+    shape = (9, 7, 11)
+    nnz, R = 400, 4
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    vals = rng.uniform(0.0, 1.0, nnz)
+    U = [None if j == mode else rng.uniform(0.0, 1.0, (s, R)) for j, s in enumerate(shape)]
+    M = oracle.mttkrp(subs, vals, shape, mode, U)
+    for r in range(R):
+        vecs = [None if j == mode else U[j][:, r] for j in range(3)]
+        assert np.array_equal(M[:, r], oracle.allbut(subs, vals, shape, mode, vecs))
+
+
+def test_mttkrp_integer_exact():
+    rng = np.random.default_rng(5)
+    shape = (6, 8, 5, 4)
+    nnz, R, mode = 500, 3, 1
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in shape])
+    vals = rng.integers(-5, 6, nnz)
+    U = _factors(rng, shape, R, mode, "int")
+    want = np.zeros((shape[mode], R), dtype=np.int64)
+    for e in range(nnz):
+        for r in range(R):
+            t = int(vals[e])
+            for j in range(4):
+                if j != mode:
+                    t *= int(U[j][subs[e, j], r])
+            want[subs[e, mode], r] += t
+    got = oracle.mttkrp(subs, vals.astype(np.float64), shape, mode, U)
+    assert np.array_equal(got, want.astype(np.float64))
