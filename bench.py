@@ -137,6 +137,64 @@ def reuse_comparison(X, subs, vals, v, K, ttv_us):
                        "achieved": alg / (kern_ms * 1e-3) / 1e9, "frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
+def mttkrp_measure(X, subs, vals, K, R=16, mode=0):
+    """Sparse MTTKRP on the bench tensor (mode 0, R = 16 U[0,1) factor
+    columns): setup (the sort by the mode's index) once, then K applies timed
+    with events and the streaming kernel with the library's per-launch
+    events.  HBM algorithmic bytes per apply: value, two 32-bit indices and a
+    row-start bit per nonzero, the factors read once and M written once; the
+    kernel is bound instead by the factor-row gathers, R * 8 bytes per
+    nonzero and other mode, served from L2 (reported as gather_bytes)."""
+    import numpy as np
+    import torch
+    from ctypes import c_void_p
+    import oracle
+    import synth
+    import paper_2510_01495_amd as P
+    from paper_2510_01495_amd import _lib as L
+    rng = np.random.default_rng(16)
+    facs = [None if j == mode else rng.uniform(0.0, 1.0, (s, R)) for j, s in enumerate(X.shape)]
+    gf = [None if U is None else torch.from_numpy(U).cuda() for U in facs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = P.MTTKRP(subs, vals, X.shape, mode, R)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    op.apply(gf)
+    torch.cuda.synchronize()
+    lib = L.load()
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for e in ev_s + ev_e:
+        e.record()
+    torch.cuda.synchronize()
+    cs = (c_void_p * K)(*[e.cuda_event for e in ev_s])
+    ce = (c_void_p * K)(*[e.cuda_event for e in ev_e])
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    L.check(lib.ttv_profile_events(L.PROF_MTTKRP, cs, ce, K), "ttv_profile_events")
+    s0.record()
+    for _ in range(K):
+        op.apply(gf)
+    s1.record()
+    torch.cuda.synchronize()
+    nrec = min(lib.ttv_profile_count(), K)
+    lib.ttv_profile_events(L.PROF_NONE, None, None, 0)
+    apply_ms = s0.elapsed_time(s1) / K
+    kern_ms = sum(ev_s[i].elapsed_time(ev_e[i]) for i in range(nrec)) / max(1, nrec)
+    M = op.M.cpu().numpy()
+    rows = rng.choice(X.shape[mode], 20, replace=False)
+    sel = np.isin(X.subs[:, mode], rows)
+    want = oracle.mttkrp(X.subs[sel], X.vals[sel], X.shape, mode, facs)[rows]
+    err = float(np.max(np.abs(M[rows] - want) / np.abs(want)))
+    nnz, d = X.nnz, len(X.shape)
+    alg = nnz * (8 + 4 * (d - 1)) + nnz / 8 + sum(X.shape) * R * 8
+    gather = nnz * (d - 1) * R * 8
+    return {"mode": mode, "R": R, "setup_ms": setup_ms, "ms_per_apply": apply_ms,
+            "nnz_per_s": nnz / (apply_ms * 1e-3), "max_rel_err_sampled": err,
+            "kernel": {"name": "k_mttkrp_apply", "avg_launch_us": kern_ms * 1e3, "alg_bytes_per_launch": alg,
+                       "achieved_hbm": alg / (kern_ms * 1e-3) / 1e9, "gather_bytes_per_launch": gather,
+                       "achieved_gather": gather / (kern_ms * 1e-3) / 1e9, "unit": "GB/s"}}
+
+
 def batched_comparison(steps):
     import numpy as np
     import torch
@@ -338,6 +396,7 @@ def main():
     t1e.record()
     torch.cuda.synchronize()
     out["plan_reuse"] = reuse_comparison(X, subs, vals, gv[0], K, t0e.elapsed_time(t1e) / K * 1e3)
+    out["mttkrp"] = mttkrp_measure(X, subs, vals, K)
     if not args.no_batch:
         out["batched"] = batched_comparison(max(3, K // 2))
     print(json.dumps(out), flush=True)

@@ -307,6 +307,47 @@ int ttv_reuse_apply(const ttv_reuse_plan* plan, const void* v, int64_t v_len, vo
                     ttv_stream_t stream);
 void ttv_reuse_plan_destroy(ttv_reuse_plan* plan);
 
+/* ------------------------------------------------------------------------
+ * Sparse MTTKRP (the matricized tensor times Khatri-Rao product the paper
+ * names as its next target; it extends Eq. 3's per-nonzero product to one
+ * factor row per mode):
+ *   M[i, r] = sum over nonzeros e with subs(e, mode) = i of
+ *             vals[e] * prod_{j != mode} U_j[subs(e, j), r]      (r < R)
+ * (factors multiplied in ascending mode order), a dense shape[mode] x R
+ * row-major matrix; rows no nonzero reaches are 0.  The tensor is fixed
+ * across calls, as in CP-ALS: the sort by the mode's index runs once.
+ *   ttv_mttkrp_plan_create  host only: validates X (as ttv_coo, d >= 2), mode
+ *                           and 1 <= R <= 256; every other mode's length must
+ *                           be at most 2^32 (TTV_E_SIZE).  X's arrays must stay
+ *                           valid until setup has run on the stream.
+ *   ttv_mttkrp_sizes        bytes of the persistent plan buffer `data` (about
+ *                           8 + 4 (d-1) + 1/8 bytes per nonzero for FP64
+ *                           values, plus 8 R + 16 bytes per 128 nonzeros) and
+ *                           of the setup workspace (free after setup).
+ *   ttv_mttkrp_setup        sorts X by the mode's index and fills `data`.
+ *                           Device errors (TTV_VALIDATE) are read with
+ *                           ttv_check_device_error(ws, stream).
+ *   ttv_mttkrp_apply        factors: host array of d device pointers, factor
+ *                           j is shape[j] x R row-major of X's value type
+ *                           (factors[mode] is ignored); M: device, shape[mode]
+ *                           x R values (FP64, or FP32 for TTV_F32 unless the
+ *                           plan was made with TTV_OUT_F64).  FP64 sums, or
+ *                           compensated (Dot2) FP32 sums per row segment with
+ *                           FP64 across segments.  Every sum has one fixed
+ *                           order (bitwise repeatable).  No allocation, no
+ *                           host synchronisation.  Applies on one plan share
+ *                           its buffer: calls that overlap on different
+ *                           streams race.
+ * ---------------------------------------------------------------------- */
+typedef struct ttv_mttkrp_plan ttv_mttkrp_plan;
+int ttv_mttkrp_plan_create(const ttv_coo_desc* X, int32_t mode, int32_t R, int32_t flags,
+                           ttv_mttkrp_plan** plan);
+int ttv_mttkrp_sizes(const ttv_mttkrp_plan* plan, size_t* data_bytes, size_t* setup_ws_bytes);
+int ttv_mttkrp_setup(ttv_mttkrp_plan* plan, void* data, size_t data_bytes, void* ws, size_t ws_bytes,
+                     ttv_stream_t stream);
+int ttv_mttkrp_apply(const ttv_mttkrp_plan* plan, const void* const* factors, void* M, ttv_stream_t stream);
+void ttv_mttkrp_plan_destroy(ttv_mttkrp_plan* plan);
+
 /*
  * Measurement hook.  While set, the library records the caller's HIP events
  * starts[k] / stops[k] on the launch stream around the k-th launch of one of
@@ -316,7 +357,8 @@ void ttv_reuse_plan_destroy(ttv_reuse_plan* plan);
  * kernel; TTV_PROF_SCATTER1 the first-level bucket scatter; TTV_PROF_HIST1
  * its histogram; TTV_PROF_DENSE the dense accumulation kernel;
  * TTV_PROF_REUSE the streaming kernel of ttv_reuse_apply; TTV_PROF_FULL the
- * streaming kernel of ttv_coo_full.  Not thread-safe;
+ * streaming kernel of ttv_coo_full; TTV_PROF_MTTKRP the streaming kernel of
+ * ttv_mttkrp_apply.  Not thread-safe;
  * for measurement only.  ttv_profile_count returns k.
  */
 enum {
@@ -326,7 +368,8 @@ enum {
   TTV_PROF_HIST1 = 3,
   TTV_PROF_DENSE = 4,
   TTV_PROF_REUSE = 5,
-  TTV_PROF_FULL = 6
+  TTV_PROF_FULL = 6,
+  TTV_PROF_MTTKRP = 7
 };
 int ttv_profile_events(int32_t kernel, void* const* starts, void* const* stops, int32_t capacity);
 int ttv_profile_count(void);

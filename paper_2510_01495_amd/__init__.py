@@ -11,11 +11,13 @@ from .api import (  # noqa: F401
     AllButOp,
     BatchedTTV,
     FullOp,
+    MTTKRP,
     ReuseTTV,
     TTVAllButFunction,
     TTVFunction,
     TTVOp,
     coo_desc,
+    mttkrp,
     plan_query,
     ttv,
     ttv_allbut,
@@ -25,5 +27,5 @@ from .api import (  # noqa: F401
     ttv_pyttb,
 )
 
-__all__ = ["AllButOp", "BatchedTTV", "FullOp", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
-           "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]
+__all__ = ["AllButOp", "BatchedTTV", "FullOp", "MTTKRP", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
+           "mttkrp", "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]

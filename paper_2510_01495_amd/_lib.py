@@ -17,7 +17,7 @@ I32, I64 = 0, 1
 F32, F64 = 0, 1
 VALIDATE, OUT_F64, DROP_ZEROS = 0x1, 0x2, 0x4
 BWD_SPARSE, BWD_ALLBUT = 0, 1
-PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE, PROF_REUSE, PROF_FULL = 0, 1, 2, 3, 4, 5, 6
+PROF_NONE, PROF_FINISH, PROF_SCATTER1, PROF_HIST1, PROF_DENSE, PROF_REUSE, PROF_FULL, PROF_MTTKRP = range(8)
 
 
 class CooDesc(ctypes.Structure):
@@ -75,6 +75,11 @@ SIGNATURES = {
                                   c_void_p]),
     "ttv_reuse_apply": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "ttv_reuse_plan_destroy": (None, [c_void_p]),
+    "ttv_mttkrp_plan_create": (c_int32, [POINTER(CooDesc), c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+    "ttv_mttkrp_sizes": (c_int32, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
+    "ttv_mttkrp_setup": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
+    "ttv_mttkrp_apply": (c_int32, [c_void_p, POINTER(c_void_p), c_void_p, c_void_p]),
+    "ttv_mttkrp_plan_destroy": (None, [c_void_p]),
     "ttv_check_device_error": (c_int32, [c_void_p, c_void_p]),
     "ttv_profile_events": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p), c_int32]),
     "ttv_profile_count": (c_int32, []),

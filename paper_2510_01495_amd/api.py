@@ -489,3 +489,69 @@ class ReuseTTV:
         if plan is not None and plan.value:
             self.lib.ttv_reuse_plan_destroy(plan)
             self.plan = None
+
+
+class MTTKRP:
+    """Sparse MTTKRP of one tensor in one mode with new factor matrices each
+    call (CP-ALS style):
+        M[i, r] = sum over nonzeros e with subs(e, mode) = i of
+                  vals[e] * prod_{j != mode} U_j[subs(e, j), r].
+    The constructor sorts the tensor by the mode's index once; ``apply``
+    enqueues one streaming pass that writes the dense (shape[mode], R) matrix
+    ``M`` and returns without synchronising.  The tensor's arrays are not
+    needed after the constructor returns."""
+
+    def __init__(self, subs, vals, shape, mode: int, R: int, *, flags: int = 0, out_f64: bool = False):
+        self.lib = L.load()
+        self.shape = tuple(int(s) for s in shape)
+        self.mode, self.R = int(mode), int(R)
+        self.flags = flags | (L.OUT_F64 if out_f64 else 0)
+        self.vdtype = vals.dtype
+        desc = coo_desc(subs, vals, self.shape)
+        self.plan = c_void_p()
+        L.check(self.lib.ttv_mttkrp_plan_create(byref(desc), self.mode, self.R, self.flags, byref(self.plan)),
+                "ttv_mttkrp_plan_create")
+        nd, nw = c_size_t(0), c_size_t(0)
+        L.check(self.lib.ttv_mttkrp_sizes(self.plan, byref(nd), byref(nw)), "ttv_mttkrp_sizes")
+        dev = subs.device
+        self.data = torch.empty(max(1, nd.value), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(1, nw.value), dtype=torch.uint8, device=dev)
+        L.check(self.lib.ttv_mttkrp_setup(self.plan, self.data.data_ptr(), self.data.numel(), ws.data_ptr(),
+                                          ws.numel(), _stream(dev)), "ttv_mttkrp_setup")
+        L.check(self.lib.ttv_check_device_error(ws.data_ptr(), _stream(dev)), "device")
+        self.M = torch.empty((self.shape[self.mode], self.R), dtype=_out_value_dtype(vals, out_f64), device=dev)
+        self.factors = None
+
+    def apply(self, factors):
+        d = len(self.shape)
+        if len(factors) != d:
+            raise ValueError("one factor per mode (the entry of `mode` is ignored)")
+        keep = [None] * d
+        ptrs = (c_void_p * d)()
+        for j, U in enumerate(factors):
+            if j == self.mode or U is None:
+                continue
+            _check_tensor(U, f"factors[{j}]")
+            if U.dtype != self.vdtype:
+                raise TypeError("factors must have the dtype of vals")
+            if tuple(U.shape) != (self.shape[j], self.R):
+                raise ValueError(f"factors[{j}] must be (shape[{j}], R)")
+            keep[j] = U.contiguous()
+            ptrs[j] = keep[j].data_ptr()
+        self.factors = keep  # kept alive until the next apply
+        L.check(self.lib.ttv_mttkrp_apply(self.plan, ptrs, self.M.data_ptr(), _stream(self.M.device)),
+                "ttv_mttkrp_apply")
+        return self.M
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan is not None and plan.value:
+            self.lib.ttv_mttkrp_plan_destroy(plan)
+            self.plan = None
+
+
+def mttkrp(subs, vals, shape, mode: int, factors, *, flags: int = 0, out_f64: bool = False):
+    """One sparse MTTKRP (sort, then one streaming pass); see ``MTTKRP``."""
+    R = next(int(U.shape[1]) for j, U in enumerate(factors) if j != mode and U is not None)
+    op = MTTKRP(subs, vals, shape, mode, R, flags=flags, out_f64=out_f64)
+    return op.apply(factors).clone()

@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "ttv.h"
+#include "ttv_carry.hpp"
 #include "ttv_device.hpp"
 #include "ttv_host.h"
 
@@ -59,16 +60,6 @@ constexpr size_t kReuseHdr = 256;                       // int64 nnz_out at offs
 constexpr size_t kReuseMaxVLds = 128 * 1024;            // largest vector staged in LDS
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Carry entry e of the apply: 2c holds chunk c's first run's partial sum,
-// 2c+1 its last run's (unused when the chunk holds a single run).  Groups
-// are fixed by the plan: for an entry that opens an output row (no used entry
-// of the same row before it), the row and how many following entries belong
-// to it (entry 2c of every following chunk c whose first row is the same).
-struct Group {
-  long long row;  // -1: the entry opens no row
-  long long cnt;
-};
 
 // sv[k] = vals[perm[k]], sidx[k] = subs(perm[k], mode); heads bit k set when
 // sorted position k starts an output row; row0[c] = output row of position
@@ -102,49 +93,12 @@ __global__ __launch_bounds__(256) void k_reuse_gather(const IdxT* subs, long lon
   }
 }
 
-// The carry groups, from the output row of every sorted position.
-__global__ __launch_bounds__(256) void k_reuse_groups(const int32_t* rowid, const long long* row0, long long nnz,
-                                                      long long nchunks, Group* groups) {
-  const gptr<const int32_t> gr = to_global(rowid);
-  const long long E = 2 * nchunks;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-       e += (long long)gridDim.x * blockDim.x) {
-    const long long c = e >> 1, k0 = c * kReuseChunk;
-    const long long n = std::min<long long>(kReuseChunk, nnz - k0);
-    const long long first = gr[k0], last = gr[k0 + n - 1];
-    const long long r = (e & 1) ? (last != first ? last : -1) : first;
-    // the previous used entry's row: entry 2c's for entry 2c+1, else the
-    // previous chunk's last row
-    const long long prev = (e & 1) ? first : (c > 0 ? (long long)gr[k0 - 1] : -1);
-    Group g{-1, 0};
-    if (r >= 0 && r != prev) {
-      long long lo = c + 1, hi = nchunks;  // first chunk after c whose first row exceeds r
-      while (lo < hi) {
-        const long long mid = (lo + hi) >> 1;
-        if (row0[mid] > r)
-          hi = mid;
-        else
-          lo = mid + 1;
-      }
-      g = Group{r, lo - (c + 1)};
-    }
-    groups[e] = g;
-  }
-}
-
-// A wave-uniform 64-bit value moved to scalar registers.
-__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
 struct ReuseArgs {
   const void* sv;
   const void* sidx;
   const unsigned long long* heads;
   const long long* row0;
-  const Group* groups;
+  const CarryGroup* groups;
   double* carry;
   const void* v;
   void* out;
@@ -277,7 +231,7 @@ __global__ __launch_bounds__(256) void k_reuse_combine(ReuseArgs A) {
   const long long E = 2 * A.nchunks;
   const gptr<const double> cv = to_global(static_cast<const double*>(A.carry));
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  Group g{-1, 0};
+  CarryGroup g{-1, 0};
   double s = 0.0;
   if (e < E) {
     g.row = to_global(A.groups)[e].row;
@@ -345,7 +299,7 @@ int ttv_reuse_plan_create(const ttv_coo_desc* X, int32_t mode, int32_t flags, tt
   p->off_row0 = o;
   o = align256(o + (size_t)p->nchunks * 8);
   p->off_groups = o;
-  o = align256(o + (size_t)(2 * p->nchunks) * sizeof(Group));
+  o = align256(o + (size_t)(2 * p->nchunks) * sizeof(CarryGroup));
   p->off_carry = o;
   o = align256(o + (size_t)(2 * p->nchunks) * sizeof(double));
   p->data_bytes = o;
@@ -418,9 +372,9 @@ int ttv_reuse_setup(ttv_reuse_plan* plan, void* data, size_t data_bytes, void* o
     by_val((int)0);
   if (plan->nnz > 0) {
     const long long ge = std::min<long long>((2 * plan->nchunks + 255) / 256, 4LL * P.cus);
-    hipLaunchKernelGGL(k_reuse_groups, dim3((unsigned)ge), dim3(256), 0, s, rowid,
+    hipLaunchKernelGGL(k_carry_groups<kReuseChunk>, dim3((unsigned)ge), dim3(256), 0, s, rowid,
                        static_cast<const long long*>(row0), plan->nnz, plan->nchunks,
-                       reinterpret_cast<Group*>(d + plan->off_groups));
+                       reinterpret_cast<CarryGroup*>(d + plan->off_groups));
   }
   plan->cus = P.cus;
   const hipError_t e = hipGetLastError();
@@ -447,7 +401,7 @@ int ttv_reuse_apply(const ttv_reuse_plan* plan, const void* v, int64_t v_len, vo
   A.sidx = d + plan->off_sidx;
   A.heads = reinterpret_cast<const unsigned long long*>(d + plan->off_heads);
   A.row0 = reinterpret_cast<const long long*>(d + plan->off_row0);
-  A.groups = reinterpret_cast<const Group*>(d + plan->off_groups);
+  A.groups = reinterpret_cast<const CarryGroup*>(d + plan->off_groups);
   A.carry = reinterpret_cast<double*>(d + plan->off_carry);
   A.v = v;
   A.out = out_vals;

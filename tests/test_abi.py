@@ -198,3 +198,36 @@ def test_densify_host_checks():
     assert lib.ttv_result_densify(2, shape, L.I64, L.F64, v, v, v, v, -1, v, None) == -12
     bad = (ctypes.c_int64 * 2)(3, 0)
     assert lib.ttv_result_densify(2, bad, L.I64, L.F64, v, v, v, v, 12, v, None) == -4
+
+
+def test_mttkrp_plan_host_checks():
+    """MTTKRP plans: argument checks and buffer sizes, host only."""
+    L, lib = _lib()
+    E = dict(NULL=-1, ORDER=-2, MODE=-3, WORKSPACE=-7, ARG=-12)
+    plan = ctypes.c_void_p()
+    d = _desc((50, 60, 70), 10_000)
+    assert lib.ttv_mttkrp_plan_create(ctypes.byref(d), 3, 8, 0, ctypes.byref(plan)) == E["MODE"]
+    assert lib.ttv_mttkrp_plan_create(ctypes.byref(d), 0, 0, 0, ctypes.byref(plan)) == E["ARG"]
+    assert lib.ttv_mttkrp_plan_create(ctypes.byref(d), 0, 257, 0, ctypes.byref(plan)) == E["ARG"]
+    assert lib.ttv_mttkrp_plan_create(ctypes.byref(_desc((5,), 3)), 0, 4, 0, ctypes.byref(plan)) == E["ORDER"]
+    assert lib.ttv_mttkrp_plan_create(ctypes.byref(d), 0, 4, L.DROP_ZEROS, ctypes.byref(plan)) == E["ARG"]
+    assert not plan.value
+    nnz, R = 10_000_000, 16
+    big = _desc((10_000,) * 3, nnz)
+    assert lib.ttv_mttkrp_plan_create(ctypes.byref(big), 1, R, 0, ctypes.byref(plan)) == 0 and plan.value
+    try:
+        nd, nw = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        assert lib.ttv_mttkrp_sizes(plan, ctypes.byref(nd), ctypes.byref(nw)) == 0
+        # values, two 32-bit index arrays, row-start bits; per 128-position unit its first row,
+        # two carry groups and two R-wide carries; the row indices
+        units = nnz // 128 + 1
+        base = nnz * (8 + 2 * 4) + nnz // 8
+        assert base <= nd.value <= base + units * (8 + 2 * 16 + 2 * R * 8) + 10_000 * 8 + 10 * 256
+        v = ctypes.c_void_p(1)
+        facs = (ctypes.c_void_p * 3)(1, 1, 1)
+        assert lib.ttv_mttkrp_apply(plan, facs, v, None) == E["ARG"]  # before setup
+        assert lib.ttv_mttkrp_setup(plan, v, 16, v, nw.value, None) == E["WORKSPACE"]
+        assert lib.ttv_mttkrp_setup(plan, v, nd.value, v, 16, None) == E["WORKSPACE"]
+    finally:
+        lib.ttv_mttkrp_plan_destroy(plan)
+    lib.ttv_mttkrp_plan_destroy(None)
