@@ -195,6 +195,124 @@ def mttkrp_measure(X, subs, vals, K, R=16, mode=0):
                        "achieved_gather": gather / (kern_ms * 1e-3) / 1e9, "unit": "GB/s"}}
 
 
+def _time_calls(fn, reps, flush=None):
+    """Mean ms per call of fn over reps, HIP events around each call; with
+    `flush`, a 1 GiB write runs before every call (outside its events) so the
+    256 MB last-level cache holds none of the inputs."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        if flush is not None:
+            flush.zero_()
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"mean_ms": sum(t) / len(t), "median_ms": t[len(t) // 2], "min_ms": t[0]}
+
+
+def other_configs(X, ops, reps):
+    """The other measured configurations: a small call's latency, cold
+    (last-level cache flushed) reps of the 1e7-nnz product, the Zipf-skewed
+    compensated FP32 product beside plain FP64 on the same tensor, the
+    all-but-one product and its adjoint of the gradient workload, and the
+    paper's n^3 density-0.01 sweep (mode 1).  Every product's sampled rows
+    are checked against the oracle."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    import paper_2510_01495_amd as P
+    from paper_2510_01495_amd import _lib as L
+    dev = torch.device("cuda:0")
+    res = {}
+    # small: 1e4 nonzeros, mode 2, FP64 (launch-latency bound)
+    Xs, ms, vs = synth.workload_small()
+    op = P.TTVOp(torch.from_numpy(Xs.subs).to(dev), torch.from_numpy(Xs.vals).to(dev), Xs.shape, [ms],
+                 [torch.from_numpy(vs).to(dev)])
+    op.launch()
+    torch.cuda.synchronize()
+    t = _time_calls(op.launch, 50)
+    gs, gv, _ = op.result()
+    res["small_1e4"] = {"us_per_call": t["mean_ms"] * 1e3, "median_us": t["median_ms"] * 1e3,
+                        "max_rel_err_sampled": sampled_error(Xs, ms, vs, gs, gv, 200, 1)}
+    # cold reps of the bench product (mode 0)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    tc = _time_calls(ops[0].launch, reps, flush)
+    tw = _time_calls(ops[0].launch, reps)
+    res["uniform_1e7_mode0"] = {"cold": tc, "warm": tw, "cold_nnz_per_s": X.nnz / (tc["mean_ms"] * 1e-3)}
+    del flush
+    # Zipf-skewed 5e7 nonzeros: compensated FP32 and plain FP64 on the same tensor
+    t0 = time.perf_counter()
+    Z, mz, vz = synth.workload_zipf()
+    gen_s = time.perf_counter() - t0
+    zs = torch.from_numpy(Z.subs).to(dev)
+    zv = torch.from_numpy(Z.vals).to(dev)
+    zvec = torch.from_numpy(vz).to(dev)
+    op32 = P.TTVOp(zs, zv, Z.shape, [mz], [zvec], out_f64=True)
+    op32.launch()
+    torch.cuda.synchronize()
+    t32 = _time_calls(op32.launch, max(3, reps // 2))
+    s32, v32, _ = op32.result()
+    err32 = sampled_error(Z, mz, vz, s32, v32, 200, 2)
+    nout = int(s32.shape[0])
+    del op32, s32, v32
+    torch.cuda.empty_cache()
+    op64 = P.TTVOp(zs.long(), zv.double(), Z.shape, [mz], [zvec.double()])
+    op64.launch()
+    torch.cuda.synchronize()
+    t64 = _time_calls(op64.launch, max(3, reps // 2))
+    s64, v64, _ = op64.result()
+    err64 = sampled_error(Z, mz, vz.astype(np.float64), s64, v64, 200, 3)
+    res["zipf_5e7"] = {"nnz": Z.nnz, "nnz_out": nout, "generate_s": gen_s,
+                       "compensated_fp32_ms": t32["mean_ms"], "fp64_ms": t64["mean_ms"],
+                       "compensated_nnz_per_s": Z.nnz / (t32["mean_ms"] * 1e-3),
+                       "speedup_fp32_vs_fp64": t64["mean_ms"] / t32["mean_ms"],
+                       "max_rel_err_sampled_fp32": err32, "max_rel_err_sampled_fp64": err64}
+    del op64, s64, v64, zs, zv, zvec, Z
+    torch.cuda.empty_cache()
+    # gradient workload: all-but-one keeping mode 0 and its adjoint, FP32
+    G, keep, gvecs, target = synth.workload_grad()
+    gsb = torch.from_numpy(G.subs).to(dev)
+    gvl = torch.from_numpy(G.vals).to(dev)
+    gvv = [None if w is None else torch.from_numpy(w).to(dev) for w in gvecs]
+    ab = P.AllButOp(gsb, gvl, G.shape, keep, gvv)
+    ab.launch()
+    torch.cuda.synchronize()
+    tf = _time_calls(ab.launch, reps)
+    gy = torch.from_numpy(target).to(dev)
+    P.ttv_backward(gsb, gvl, G.shape, "allbut", keep, gvv, gy)
+    torch.cuda.synchronize()
+    tb = _time_calls(lambda: P.ttv_backward(gsb, gvl, G.shape, "allbut", keep, gvv, gy), max(3, reps // 2))
+    y = ab.y.double().cpu().numpy()
+    rows = np.random.default_rng(4).choice(G.shape[keep], 50, replace=False)
+    sel = np.isin(G.subs[:, keep], rows)
+    want = oracle.allbut(G.subs[sel], G.vals[sel], G.shape, keep, gvecs)[rows]
+    scale = oracle.allbut_abs(G.subs[sel], G.vals[sel], G.shape, keep, gvecs)[rows]
+    res["grad_2e7"] = {"allbut_fp32_ms": tf["mean_ms"], "backward_fp32_ms": tb["mean_ms"],
+                       "allbut_nnz_per_s": G.nnz / (tf["mean_ms"] * 1e-3),
+                       "max_err_over_abs_sum_sampled": float(np.max(np.abs(y[rows] - want) / scale))}
+    del ab, gsb, gvl, gvv, G
+    torch.cuda.empty_cache()
+    # the paper's sweep: n^3 at density 0.01, FP64, mode 1
+    sweep = {}
+    for n in (400, 800, 1200):
+        W, mw, vw = synth.workload_paper_sweep(n)
+        opw = P.TTVOp(torch.from_numpy(W.subs).to(dev), torch.from_numpy(W.vals).to(dev), W.shape, [mw],
+                      [torch.from_numpy(vw).to(dev)])
+        opw.launch()
+        torch.cuda.synchronize()
+        tw_ = _time_calls(opw.launch, reps)
+        ws_, wv_, _ = opw.result()
+        sweep[str(n)] = {"nnz": W.nnz, "ms": tw_["mean_ms"], "nnz_per_s": W.nnz / (tw_["mean_ms"] * 1e-3),
+                         "max_rel_err_sampled": sampled_error(W, mw, vw, ws_, wv_, 100, n)}
+        del opw, ws_, wv_, W
+        torch.cuda.empty_cache()
+    res["paper_sweep_mode1"] = sweep
+    return res
+
+
 def batched_comparison(steps):
     import numpy as np
     import torch
@@ -255,6 +373,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other measured configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (the reference for HBM counters)")
     args = ap.parse_args()
@@ -397,6 +516,8 @@ def main():
     torch.cuda.synchronize()
     out["plan_reuse"] = reuse_comparison(X, subs, vals, gv[0], K, t0e.elapsed_time(t1e) / K * 1e3)
     out["mttkrp"] = mttkrp_measure(X, subs, vals, K)
+    if not args.no_configs:
+        out["configs"] = other_configs(X, ops, K)
     if not args.no_batch:
         out["batched"] = batched_comparison(max(3, K // 2))
     print(json.dumps(out), flush=True)

@@ -400,6 +400,37 @@ __global__ __launch_bounds__(1024) void k_colscan(WsView W, int level) {
   const int njobs = clampi(C->njobs[level], W.L.jcap);
   const Job* jobs = W.jobs(level);
   unsigned* table = W.table();
+  if (level > 1) {
+    // deeper levels: many jobs of few tiles each -- one job per block, one
+    // digit column per thread, its tiles in order
+    for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+      const Job J = jobs[j];
+      const int nd = 1 << J.r;
+      for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+        unsigned run = 0;
+        long long t = J.tile0;
+        const long long te = J.tile0 + J.ntiles;
+        for (; t + 8 <= te; t += 8) {
+          unsigned c[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) c[k] = table[(size_t)(t + k) * kNDig + d];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            table[(size_t)(t + k) * kNDig + d] = run;
+            run += c[k];
+          }
+        }
+        for (; t < te; ++t) {
+          unsigned* p = &table[(size_t)t * kNDig + d];
+          const unsigned c = *p;
+          *p = run;
+          run += c;
+        }
+        W.starts()[(size_t)j * kNDig + d] = run;
+      }
+    }
+    return;
+  }
   const int dd = threadIdx.x & 63, g = threadIdx.x >> 6;
   for (long long it = blockIdx.x; it < (long long)njobs * 64; it += gridDim.x) {
     const int j = (int)(it >> 6), ch = (int)(it & 63);
