@@ -27,6 +27,7 @@ constexpr int kScatterThreads = 256;     // 4 waves
 constexpr int kHistThreads = 1024;       // 16 waves
 constexpr int kBitmapWordsPerBlock = 2048;  // leaf-start bitmap words per block: 256 threads x 8
 constexpr int kHistIPT = 4;
+constexpr int kFewTiles = 16;            // deeper-level jobs of at most this many tiles: column scan per thread
 constexpr int kScatterIPT = 8;           // records per thread per round
 constexpr int kFinishThreads = 512;     // 8 waves
 constexpr int kFinishIPT = kCap / kFinishThreads;

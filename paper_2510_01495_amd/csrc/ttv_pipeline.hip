@@ -393,79 +393,105 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(WsView W, int level, int 
 // job's tiles, in tile order (in place); digit totals go to starts[job].
 // Block = 64 digits x 16 tile groups.
 // ---------------------------------------------------------------------------
+// Column scan of one 64-digit chunk of job j: the tiles split in 16 groups,
+// each group sums its tiles' counts, then every group rewrites its tiles'
+// counts as running offsets (exclusive, in tile order); starts gets the
+// digit totals.
+__device__ __forceinline__ void colscan_chunk(WsView W, const Job& J, int j, int ch, unsigned (&part)[16][64]) {
+  unsigned* table = W.table();
+  const int dd = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int nd = 1 << J.r;
+  const int d = ch * 64 + dd;
+  const bool act = d < nd;
+  const int per = (J.ntiles + 15) / 16;
+  const long long t0 = J.tile0 + (long long)g * per;
+  long long t1 = t0 + per;
+  if (t1 > J.tile0 + J.ntiles) t1 = J.tile0 + J.ntiles;
+  unsigned s = 0;
+  if (act) {
+#pragma unroll 8
+    for (long long t = t0; t < t1; ++t) s += table[(size_t)t * kNDig + d];
+  }
+  part[g][dd] = s;
+  __syncthreads();
+  unsigned off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const unsigned v = part[q][dd];
+    off += (q < g) ? v : 0u;
+    tot += v;
+  }
+  if (act) {
+    unsigned run = off;
+    for (long long t = t0; t < t1; ++t) {
+      unsigned* p = &table[(size_t)t * kNDig + d];
+      const unsigned c = *p;
+      *p = run;
+      run += c;
+    }
+    if (g == 0) W.starts()[(size_t)j * kNDig + d] = tot;
+  }
+  __syncthreads();
+}
+
+// Column scan of one job of at most kFewTiles tiles: one digit column per
+// thread, its tiles in order.
+__device__ __forceinline__ void colscan_serial(WsView W, const Job& J, int j) {
+  unsigned* table = W.table();
+  const int nd = 1 << J.r;
+  for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+    unsigned c[kFewTiles];
+#pragma unroll
+    for (int k = 0; k < kFewTiles; ++k) c[k] = k < J.ntiles ? table[(size_t)(J.tile0 + k) * kNDig + d] : 0u;
+    unsigned run = 0;
+#pragma unroll
+    for (int k = 0; k < kFewTiles; ++k)
+      if (k < J.ntiles) {
+        table[(size_t)(J.tile0 + k) * kNDig + d] = run;
+        run += c[k];
+      }
+    W.starts()[(size_t)j * kNDig + d] = run;
+  }
+}
+
+// Per-(tile, digit) bucket offsets and per-job digit totals.  Level 1 has a
+// few jobs of many tiles: items are (job, 64-digit chunk).  Deeper levels
+// have many jobs, mostly of few tiles: one block per such job; the jobs with
+// more tiles are listed per batch of 1024 jobs and their (job, chunk) items
+// spread over the blocks.
 __global__ __launch_bounds__(1024) void k_colscan(WsView W, int level) {
   __shared__ unsigned part[16][64];
+  __shared__ int bigs[1024];
+  __shared__ unsigned wsum[1024 / 64];
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int njobs = clampi(C->njobs[level], W.L.jcap);
   const Job* jobs = W.jobs(level);
-  unsigned* table = W.table();
-  if (level > 1) {
-    // deeper levels: many jobs of few tiles each -- one job per block, one
-    // digit column per thread, its tiles in order
-    for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+  if (level == 1) {
+    for (long long it = blockIdx.x; it < (long long)njobs * 64; it += gridDim.x) {
+      const int j = (int)(it >> 6), ch = (int)(it & 63);
       const Job J = jobs[j];
-      const int nd = 1 << J.r;
-      for (int d = threadIdx.x; d < nd; d += blockDim.x) {
-        unsigned run = 0;
-        long long t = J.tile0;
-        const long long te = J.tile0 + J.ntiles;
-        for (; t + 8 <= te; t += 8) {
-          unsigned c[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) c[k] = table[(size_t)(t + k) * kNDig + d];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            table[(size_t)(t + k) * kNDig + d] = run;
-            run += c[k];
-          }
-        }
-        for (; t < te; ++t) {
-          unsigned* p = &table[(size_t)t * kNDig + d];
-          const unsigned c = *p;
-          *p = run;
-          run += c;
-        }
-        W.starts()[(size_t)j * kNDig + d] = run;
-      }
+      if (ch * 64 >= (1 << J.r)) continue;  // uniform over the block
+      colscan_chunk(W, J, j, ch, part);
     }
     return;
   }
-  const int dd = threadIdx.x & 63, g = threadIdx.x >> 6;
-  for (long long it = blockIdx.x; it < (long long)njobs * 64; it += gridDim.x) {
-    const int j = (int)(it >> 6), ch = (int)(it & 63);
+  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
     const Job J = jobs[j];
-    const int nd = 1 << J.r;
-    if (ch * 64 >= nd) continue;  // uniform over the block
-    const int d = ch * 64 + dd;
-    const bool act = d < nd;
-    const int per = (J.ntiles + 15) / 16;
-    const long long t0 = J.tile0 + (long long)g * per;
-    long long t1 = t0 + per;
-    if (t1 > J.tile0 + J.ntiles) t1 = J.tile0 + J.ntiles;
-    unsigned s = 0;
-    if (act) {
-#pragma unroll 8
-      for (long long t = t0; t < t1; ++t) s += table[(size_t)t * kNDig + d];
-    }
-    part[g][dd] = s;
+    if (J.ntiles <= kFewTiles) colscan_serial(W, J, j);
+  }
+  for (int jb = 0; jb < njobs; jb += 1024) {
+    const int j = jb + (int)threadIdx.x;
+    const bool big = j < njobs && jobs[j].ntiles > kFewTiles;
+    unsigned nbig;
+    const unsigned pos = block_excl_scan<1024>(big ? 1u : 0u, wsum, nbig);
+    if (big) bigs[pos] = j;
     __syncthreads();
-    unsigned off = 0, tot = 0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const unsigned v = part[q][dd];
-      off += (q < g) ? v : 0u;
-      tot += v;
-    }
-    if (act) {
-      unsigned run = off;
-      for (long long t = t0; t < t1; ++t) {
-        unsigned* p = &table[(size_t)t * kNDig + d];
-        const unsigned c = *p;
-        *p = run;
-        run += c;
-      }
-      if (g == 0) W.starts()[(size_t)j * kNDig + d] = tot;
+    for (long long it = blockIdx.x; it < (long long)nbig * 64; it += gridDim.x) {
+      const int jj = bigs[it >> 6], ch = (int)(it & 63);
+      const Job J = jobs[jj];
+      if (ch * 64 >= (1 << J.r)) continue;  // uniform over the block
+      colscan_chunk(W, J, jj, ch, part);
     }
     __syncthreads();
   }
