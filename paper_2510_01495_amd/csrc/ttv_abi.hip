@@ -155,9 +155,23 @@ int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
   return TTV_OK;
 }
 
+// Bucket levels of a tensor: the first digit, then 12-bit digits for the
+// rest of the key; one more when the first level's buckets are expected to
+// be nearly full on average and the second level would be the last one
+// (it would then have to take all the remaining bits): most buckets split at
+// the second level, which takes only the few bits they need, and the level
+// after it the rest.
 static int levels_of(const TDesc& D) {
   const int rest = std::max(0, D.keybits - D.r1);
-  return std::min(kMaxLevels, 1 + (rest + kRMax - 1) / kRMax);
+  int levels = 1 + (rest + kRMax - 1) / kRMax;
+  if (rest > 0 && D.nnz > 0) {
+    unsigned __int128 range = 1;
+    for (int i = 0; i < D.nrem; ++i) range *= (unsigned __int128)D.dims[D.rem[i]];
+    const double used = (double)((range + (((unsigned __int128)1 << rest) - 1)) >> rest);
+    const bool full = (double)D.nnz / used > 0.9 * kCap;
+    if (full && levels == 2 && rest > 2) ++levels;
+  }
+  return std::min(kMaxLevels, levels);
 }
 
 Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1) {

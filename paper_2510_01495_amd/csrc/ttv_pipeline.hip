@@ -686,7 +686,18 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
           nt = 0;
           N.size = 0;
         }
-        N.r = J.shift < kRMax ? J.shift : kRMax;
+        // digit bits of the new job: enough for sub-buckets of about kSmall
+        // records, but at least what the levels after it cannot take
+        {
+          const int after = maxlevel - (level + 1);
+          const int need = J.shift - kRMax * after;
+          int rs = 1;
+          while (rs < kRMax && (size >> rs) > kSmall) ++rs;
+          int r = rs > need ? rs : need;
+          if (r > kRMax) r = kRMax;
+          if (r > J.shift) r = J.shift;
+          N.r = r;
+        }
         N.shift = J.shift - N.r;
         N.prefix = dbase;
         N.tile0 = t0;
