@@ -324,9 +324,11 @@ void ttv_reuse_plan_destroy(ttv_reuse_plan* plan);
  *                           8 + 4 (d-1) + 1/8 bytes per nonzero for FP64
  *                           values, plus 8 R + 16 bytes per 128 nonzeros) and
  *                           of the setup workspace (free after setup).
- *   ttv_mttkrp_setup        sorts X by the mode's index and fills `data`.
- *                           Device errors (TTV_VALIDATE) are read with
- *                           ttv_check_device_error(ws, stream).
+ *   ttv_mttkrp_setup        sorts X by the mode's index and fills `data`;
+ *                           synchronises the stream once at its end (to learn
+ *                           whether any row spans more than 32 units of 128
+ *                           nonzeros).  Device errors (TTV_VALIDATE) are read
+ *                           with ttv_check_device_error(ws, stream).
  *   ttv_mttkrp_apply        factors: host array of d device pointers, factor
  *                           j is shape[j] x R row-major of X's value type
  *                           (factors[mode] is ignored); M: device, shape[mode]

@@ -47,6 +47,10 @@ struct ttv_mttkrp_plan {
   long long nunits = 0;
   long long dcap = 0;  // rows the distinct-index list can hold: min(nnz, shape[mode])
   size_t off_sv = 0, off_sidx = 0, off_heads = 0, off_rank0 = 0, off_dist = 0, off_groups = 0, off_carry = 0;
+  size_t off_hier = 0;
+  int hlevels = 0;                         // unit-carry hierarchy levels above 0
+  int long_rows = 0;                       // some row spans more than kSerial units (setup)
+  long long hoff[8] = {0}, hcnt[8] = {0};  // entry offset and count of every level
   size_t data_bytes = 0;
   size_t off_perm = 0, off_rowid = 0, off_osubs = 0, setup_bytes = 0;
   void* data = nullptr;  // bound by setup
@@ -114,6 +118,9 @@ __global__ __launch_bounds__(256) void k_mttkrp_gather(GatherArgs A) {
   }
 }
 
+constexpr long long kSerial = 32;  // rows spanning at most this many more units: carries added one by one
+constexpr int kMaxHier = 6;        // hierarchy levels: 32^5 units exceed any supported nnz
+
 struct MArgs {
   const void* sv;
   const uint32_t* sidx;
@@ -123,6 +130,11 @@ struct MArgs {
   const long long* hdr;
   const CarryGroup* groups;
   double* carry;  // [2 * nunits][R]
+  double* hier;   // levels 1.. of the unit-carry hierarchy, [hoff[h] + i][R]
+  const long long* longest;  // largest row span in units (setup), 0 if none above kSerial
+  long long hoff[kMaxHier + 1];
+  long long hcnt[kMaxHier + 1];  // entries per level (hcnt[0] = nunits)
+  int hlevels;                   // levels above 0
   const void* fac[kMaxOrder];  // factor of the f-th other mode, (shape, R) row-major
   void* M;
   long long nnz, nunits, nrows;
@@ -248,8 +260,65 @@ __global__ __launch_bounds__(kMThreads) void k_mttkrp_apply(MArgs A) {
   }
 }
 
+// Entry i of hierarchy level h (R columns): level 0 is the first-run carry
+// of unit i (entry 2i), level h >= 1 the sum of 32 consecutive entries of
+// level h - 1.
+__device__ __forceinline__ const double* level_entry(const MArgs& A, int h, long long i) {
+  return h == 0 ? A.carry + (2 * i) * A.R : A.hier + (A.hoff[h] + i) * A.R;
+}
+
+// Level h of the hierarchy, one lane group per entry: its 32 level h - 1
+// entries added in order (FP64).  Skipped when no row spans more than kSerial
+// units (the largest span is computed at setup).
+template <int NC>
+__global__ __launch_bounds__(kMThreads) void k_mttkrp_level(MArgs A, int h) {
+  if (*A.longest <= kSerial) return;
+  const unsigned ln = lane_id();
+  const int GS = A.GS;
+  const int grp = (int)ln / GS, rl = (int)ln % GS;
+  const long long wv = (long long)blockIdx.x * (kMThreads / 64) + (threadIdx.x >> 6);
+  const long long b = wv * (64 / GS) + grp;
+  if (b >= A.hcnt[h]) return;
+  const long long n = A.hcnt[h - 1];
+  double s[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) s[k] = 0.0;
+  for (long long i = 32 * b; i < 32 * b + 32 && i < n; ++i) {
+    const gptr<const double> src = to_global(level_entry(A, h - 1, i));
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int r = rl + 64 * k;
+      if (r < A.R) s[k] += src[r];
+    }
+  }
+  double* dst = A.hier + (A.hoff[h] + b) * A.R;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int r = rl + 64 * k;
+    if (r < A.R) to_global(dst)[r] = s[k];
+  }
+}
+
+// Adds entries [lo, hi) of level h to s, in order.
+template <int NC>
+__device__ __forceinline__ void add_range(const MArgs& A, int h, long long lo, long long hi, int rl, double (&s)[NC]) {
+#pragma unroll 4
+  for (long long i = lo; i < hi; ++i) {
+    const gptr<const double> src = to_global(level_entry(A, h, i));
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int r = rl + 64 * k;
+      if (r < A.R) s[k] += src[r];
+    }
+  }
+}
+
 // Rows that touch a unit boundary: the entry that opens a row adds the
-// following entries of its group in order (FP64), one lane group per entry.
+// first-run carries of the next cnt units, in a fixed order (FP64), one lane
+// group per entry.  Up to kSerial of them one by one; longer spans as the
+// level-0 entries up to a multiple of 32, then the same on the next level
+// for the whole blocks, ..., and the partial blocks at the end, highest
+// level first.
 template <int NC>
 __global__ __launch_bounds__(kMThreads) void k_mttkrp_combine(MArgs A) {
   const unsigned ln = lane_id();
@@ -261,23 +330,56 @@ __global__ __launch_bounds__(kMThreads) void k_mttkrp_combine(MArgs A) {
   const long long row = to_global(A.groups)[e].row, cnt = to_global(A.groups)[e].cnt;
   if (row < 0) return;
   const gptr<const double> cv = to_global(static_cast<const double*>(A.carry));
-  const long long u1 = e >> 1;
   double s[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const int r = rl + 64 * k;
     s[k] = r < A.R ? cv[e * A.R + r] : 0.0;
   }
-#pragma unroll 4
-  for (long long q = 0; q < cnt; ++q) {
-    const long long f = 2 * (u1 + 1 + q);
+  long long lo = (e >> 1) + 1, hi = lo + cnt;  // level-0 entries of the following units
+  if (cnt <= kSerial) {
+    add_range<NC>(A, 0, lo, hi, rl, s);
+  } else {
+    double tail[kMaxHier][NC];
+    int top = 0;  // the level whose remaining range is added whole
+    bool open = true;
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int r = rl + 64 * k;
-      if (r < A.R) s[k] += cv[f * A.R + r];
+    for (int h = 0; h < kMaxHier; ++h) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) tail[h][k] = 0.0;
+      if (open && h < A.hlevels) {
+        const long long lo2 = (lo + 31) / 32, hi2 = hi / 32;
+        if (lo2 >= hi2) {  // no whole block on the next level
+          open = false;
+        } else {
+          add_range<NC>(A, h, lo, lo2 * 32, rl, s);
+          add_range<NC>(A, h, hi2 * 32, hi, rl, tail[h]);
+          lo = lo2;
+          hi = hi2;
+          top = h + 1;
+        }
+      } else {
+        open = false;
+      }
     }
+    add_range<NC>(A, top, lo, hi, rl, s);
+#pragma unroll
+    for (int h = kMaxHier - 1; h >= 0; --h)
+      if (h < top)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) s[k] += tail[h][k];
   }
   write_row<NC>(A, row, rl, s);
+}
+
+// The longest span (units after the opening entry) of any row, for skipping
+// the hierarchy when every row is short.
+__global__ __launch_bounds__(256) void k_mttkrp_longest(const CarryGroup* groups, long long E, long long* longest) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long long)gridDim.x * blockDim.x) {
+    const long long c = to_global(groups)[e].cnt;
+    if (to_global(groups)[e].row >= 0 && c > kSerial) atomicMax(reinterpret_cast<unsigned long long*>(longest),
+                                                                (unsigned long long)c);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_mttkrp_zero(void* M, long long n, int f64) {
@@ -365,6 +467,17 @@ int ttv_mttkrp_plan_create(const ttv_coo_desc* X, int32_t mode, int32_t R, int32
   o = align256(o + (size_t)(2 * p->nunits) * sizeof(CarryGroup));
   p->off_carry = o;
   o = align256(o + (size_t)(2 * p->nunits) * R * sizeof(double));
+  // hierarchy of first-run carries: level h + 1 sums 32 entries of level h
+  p->hcnt[0] = p->nunits;
+  long long hs = 0;
+  while (p->hlevels + 1 < kMaxHier && p->hcnt[p->hlevels] > 32) {
+    const int h = ++p->hlevels;
+    p->hcnt[h] = (p->hcnt[h - 1] + 31) / 32;
+    p->hoff[h] = hs;
+    hs += p->hcnt[h];
+  }
+  p->off_hier = o;
+  o = align256(o + (size_t)std::max<long long>(hs, 1) * R * sizeof(double));
   p->data_bytes = o;
   p->off_perm = align256(p->P.L.end);
   p->off_rowid = p->off_perm + align256((size_t)p->nnz * 4);
@@ -394,6 +507,7 @@ int ttv_mttkrp_setup(ttv_mttkrp_plan* plan, void* data, size_t data_bytes, void*
     // no sort: only the device error word that ttv_check_device_error reads
     if (int rc = launch_zero(w, 256, s)) return rc;
   } else {
+    if (int rc = launch_zero(d, kMHdr, s)) return rc;  // the count and the longest span
     PipePlan P = plan->P;
     P.d0.out_subs = w + plan->off_osubs;
     P.d0.out_nnz = reinterpret_cast<long long*>(d);  // the header's count
@@ -437,6 +551,19 @@ int ttv_mttkrp_setup(ttv_mttkrp_plan* plan, void* data, size_t data_bytes, void*
     hipLaunchKernelGGL(k_carry_groups<kMUnit>, dim3((unsigned)ge), dim3(256), 0, s, G.rowid,
                        static_cast<const long long*>(G.rank0), plan->nnz, plan->nunits,
                        reinterpret_cast<CarryGroup*>(d + plan->off_groups));
+    hipLaunchKernelGGL(k_mttkrp_longest, dim3((unsigned)ge), dim3(256), 0, s,
+                       reinterpret_cast<const CarryGroup*>(d + plan->off_groups), 2 * plan->nunits,
+                       reinterpret_cast<long long*>(d + 8));
+    // whether any row spans more than kSerial units: the applies launch the
+    // hierarchy kernels only then
+    long long longest = 0;
+    hipError_t e = hipMemcpyAsync(&longest, d + 8, sizeof(longest), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      set_last_hip_error((int)e);
+      return TTV_E_HIP;
+    }
+    plan->long_rows = longest > kSerial ? 1 : 0;
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -471,6 +598,13 @@ int ttv_mttkrp_apply(const ttv_mttkrp_plan* plan, const void* const* factors, vo
     A.hdr = reinterpret_cast<const long long*>(d);
     A.groups = reinterpret_cast<const CarryGroup*>(d + plan->off_groups);
     A.carry = reinterpret_cast<double*>(d + plan->off_carry);
+    A.hier = reinterpret_cast<double*>(d + plan->off_hier);
+    A.longest = reinterpret_cast<const long long*>(d + 8);
+    A.hlevels = plan->hlevels;
+    for (int h = 0; h <= kMaxHier; ++h) {
+      A.hoff[h] = h < 8 ? plan->hoff[h] : 0;
+      A.hcnt[h] = h < 8 ? plan->hcnt[h] : 0;
+    }
     for (int f = 0; f < kMaxOrder; ++f) A.fac[f] = f < plan->nf ? factors[plan->others[f]] : nullptr;
     A.M = M;
     A.nnz = plan->nnz;
@@ -492,6 +626,15 @@ int ttv_mttkrp_apply(const ttv_mttkrp_plan* plan, const void* const* factors, vo
     else
       launch_apply<kC32>(A, nc, plan->nf, dim3((unsigned)ga), s);
     prof_end(TTV_PROF_MTTKRP, s);
+    for (int h = 1; plan->long_rows && h <= plan->hlevels; ++h) {
+      const long long gh = (plan->hcnt[h] + per_wave * (kMThreads / 64) - 1) / (per_wave * (kMThreads / 64));
+      if (nc == 1)
+        hipLaunchKernelGGL(k_mttkrp_level<1>, dim3((unsigned)gh), dim3(kMThreads), 0, s, A, h);
+      else if (nc == 2)
+        hipLaunchKernelGGL(k_mttkrp_level<2>, dim3((unsigned)gh), dim3(kMThreads), 0, s, A, h);
+      else
+        hipLaunchKernelGGL(k_mttkrp_level<4>, dim3((unsigned)gh), dim3(kMThreads), 0, s, A, h);
+    }
     if (nc == 1)
       hipLaunchKernelGGL(k_mttkrp_combine<1>, dim3((unsigned)gc), dim3(kMThreads), 0, s, A);
     else if (nc == 2)

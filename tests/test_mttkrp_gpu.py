@@ -103,6 +103,30 @@ def test_empty_rows_and_heavy_rows():
     _check(X, 0, facs, M, F64_TOL, "gaps")
 
 
+@pytest.mark.parametrize("R", [3, 40, 130])
+def test_rows_spanning_thousands_of_units(R):
+    """Rows of 300000, 70000 and 4100 nonzeros (about 2300, 550 and 32
+    128-position units): their unit partial sums are added through the
+    32-ary hierarchy, in a fixed order; bitwise repeatable."""
+    P = _api()
+    rng = np.random.default_rng(30 + R)
+    shape = (12, 40, 30)
+    parts = []
+    for i, n in [(1, 300_000), (2, 5), (5, 70_000), (6, 4100), (9, 33 * 128 + 1), (11, 1)]:
+        parts.append(np.column_stack([np.full(n, i), rng.integers(0, 40, n), rng.integers(0, 30, n)]))
+    subs_np = np.vstack(parts).astype(np.int32)
+    subs_np = subs_np[rng.permutation(subs_np.shape[0])]
+    X = synth.COO(subs_np, rng.uniform(0.0, 1.0, subs_np.shape[0]), shape)
+    facs = _factors(rng, shape, R, 0, np.float64, "u01")
+    subs, vals = to_gpu(X)
+    say(f"mttkrp long rows R={R}")
+    op = P.MTTKRP(subs, vals, shape, 0, R)
+    g = _gpu(facs)
+    M1 = op.apply(g).clone()
+    _check(X, 0, facs, M1, F64_TOL, f"long rows R={R}")
+    assert np.array_equal(M1.cpu().numpy(), op.apply(g).cpu().numpy())
+
+
 def test_new_factors_and_bitwise_repeat():
     P = _api()
     rng = np.random.default_rng(22)
