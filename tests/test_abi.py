@@ -219,10 +219,12 @@ def test_mttkrp_plan_host_checks():
         nd, nw = ctypes.c_size_t(0), ctypes.c_size_t(0)
         assert lib.ttv_mttkrp_sizes(plan, ctypes.byref(nd), ctypes.byref(nw)) == 0
         # values, two 32-bit index arrays, row-start bits; per 128-position unit its first row,
-        # two carry groups and two R-wide carries; the row indices
+        # two carry groups and two R-wide carries; the row indices; the 32-ary hierarchy of
+        # unit carries (about one R-wide entry per 31 units)
         units = nnz // 128 + 1
         base = nnz * (8 + 2 * 4) + nnz // 8
-        assert base <= nd.value <= base + units * (8 + 2 * 16 + 2 * R * 8) + 10_000 * 8 + 10 * 256
+        hier = (units // 31 + 8) * R * 8
+        assert base <= nd.value <= base + units * (8 + 2 * 16 + 2 * R * 8) + hier + 10_000 * 8 + 12 * 256
         v = ctypes.c_void_p(1)
         facs = (ctypes.c_void_p * 3)(1, 1, 1)
         assert lib.ttv_mttkrp_apply(plan, facs, v, None) == E["ARG"]  # before setup
