@@ -191,6 +191,7 @@ def mttkrp_measure(X, subs, vals, K, R=16, mode=0):
     return {"mode": mode, "R": R, "setup_ms": setup_ms, "ms_per_apply": apply_ms,
             "nnz_per_s": nnz / (apply_ms * 1e-3), "max_rel_err_sampled": err,
             "kernel": {"name": "k_mttkrp_apply", "avg_launch_us": kern_ms * 1e3, "alg_bytes_per_launch": alg,
+                       "traffic": kernel_traffic("k_mttkrp_apply", "uniform1e7"),
                        "achieved_hbm": alg / (kern_ms * 1e-3) / 1e9, "gather_bytes_per_launch": gather,
                        "achieved_gather": gather / (kern_ms * 1e-3) / 1e9, "unit": "GB/s"}}
 
