@@ -332,6 +332,7 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, con
     P.d0.out_subs = out_subs;
     P.d0.out_vals = out_vals;
     P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
+    if (tiny_fits(P, flags)) return launch_tiny(P, ws, s);
     return launch_pipeline(P, ws, s);
   }
   // the product into the temporary area, then its rows with nonzero sums

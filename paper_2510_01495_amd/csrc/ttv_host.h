@@ -54,6 +54,13 @@ int launch_drop_zeros(const void* in_subs, const void* in_vals, const long long*
                       void* out_subs, void* out_vals, long long* out_nnz, int nrem, int idx64, int out_f64,
                       hipStream_t s);
 
+// Small FP64 products in one block and one launch (at most kTinyNnz nonzeros
+// and kTinyKeys distinct keys of the remaining modes).
+constexpr long long kTinyNnz = 1 << 15;
+constexpr int kTinyKeys = 8192;
+bool tiny_fits(const PipePlan& P, int flags);
+int launch_tiny(const PipePlan& P, void* ws, hipStream_t s);
+
 constexpr int kAssumedCUs = 256;  // MI355X; tiling never depends on the device queried at call time
 
 }  // namespace ttv

@@ -285,3 +285,49 @@ def test_zipf_c32_repeated_launches():
     scale = oracle.abs_sums(X.subs, X.vals, X.shape, mode, v, gs[pick])
     err = np.abs(gv[pick] - want)
     assert np.all(err <= C32_TOL * scale + 1e-300), float(np.max(err / scale))
+
+
+@pytest.mark.parametrize("nnz,shape", [(32768, (64, 50, 128)), (32769, (64, 50, 128)), (1, (3, 4, 5)),
+                                       (5000, (2, 3, 4, 5, 6, 2, 2, 3))])
+@pytest.mark.parametrize("soa", [False, True])
+def test_small_fp64_one_block_and_pipeline(nnz, shape, soa):
+    """FP64 products of at most 32768 nonzeros whose remaining modes span at
+    most 8192 keys run in one block (dense LDS sums by key); one nonzero more
+    runs the sorting pipeline.  Both against the oracle, at the edges: exactly
+    8192 keys (64 x 128), 32768 / 32769 nonzeros, one nonzero, order 8;
+    row-major and column-major subs."""
+    P = _api()
+    rng = np.random.default_rng(nnz + len(shape))
+    mode = 1
+    subs_np = np.column_stack([rng.integers(0, s, nnz) for s in shape]).astype(np.int64).reshape(nnz, len(shape))
+    X = synth.COO(subs_np, rng.standard_normal(nnz), shape)
+    v_np = rng.standard_normal(shape[mode])
+    subs, vals, v = to_gpu(X, v_np, soa=soa)
+    say(f"small fp64 nnz={nnz} d={len(shape)} soa={soa}")
+    gs, gv, _ = P.ttv(subs, vals, shape, mode, v)
+    check_ttv(X, mode, v_np, gs, gv, F64_TOL, f"small nnz={nnz}")
+    gs2, gv2, _ = P.ttv(subs, vals, shape, mode, v)
+    assert np.array_equal(gv.cpu().numpy(), gv2.cpu().numpy()), "not bitwise repeatable"
+
+
+@pytest.mark.parametrize("nnz,shape", [(3000, (20, 30, 40)), (60_000, (300, 200, 100))])
+def test_validate_reports_bad_index(nnz, shape):
+    """An index one past its dimension under TTV_VALIDATE, in the one-block
+    small path (3000 nonzeros) and in the sorting pipeline (60000): the
+    kernels read index 0 instead and record TTV_E_INDEX; the next call on
+    valid data reports no error."""
+    import torch
+    P = _api()
+    from paper_2510_01495_amd import _lib as L
+    rng = np.random.default_rng(nnz)
+    subs_np = np.column_stack([rng.integers(0, s, nnz) for s in shape]).astype(np.int64)
+    bad = subs_np.copy()
+    bad[nnz // 2, 2] = shape[2]
+    v = torch.from_numpy(rng.standard_normal(shape[1])).cuda()
+    vals = torch.from_numpy(rng.standard_normal(nnz)).cuda()
+    op = P.TTVOp(torch.from_numpy(bad).cuda(), vals, shape, [1], [v], flags=L.VALIDATE)
+    op.launch()
+    assert op.device_error() == -8
+    op = P.TTVOp(torch.from_numpy(subs_np).cuda(), vals, shape, [1], [v], flags=L.VALIDATE)
+    op.launch()
+    assert op.device_error() == 0
