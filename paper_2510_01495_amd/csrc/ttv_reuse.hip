@@ -213,7 +213,20 @@ __global__ __launch_bounds__(kReuseLdsThreads) void k_reuse_apply_lds(ReuseArgs 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   In* vs = reinterpret_cast<In*>(smem);
   const gptr<const In> gv = to_global(static_cast<const In*>(A.v));
-  for (long long i = threadIdx.x; i < A.vlen; i += kReuseLdsThreads) vs[i] = gv[i];
+  // the copy: 16 loads per thread issued together, then their LDS stores
+  for (long long b = 0; b < A.vlen; b += 16LL * kReuseLdsThreads) {
+    In t[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const long long i = b + (long long)q * kReuseLdsThreads + threadIdx.x;
+      t[q] = i < A.vlen ? gv[i] : (In)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const long long i = b + (long long)q * kReuseLdsThreads + threadIdx.x;
+      if (i < A.vlen) vs[i] = t[q];
+    }
+  }
   __syncthreads();
   constexpr int NW = kReuseLdsThreads / 64;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
