@@ -4,7 +4,8 @@
 // sparse and a dense vector (Sec. 3.1).
 //
 // One streaming pass: a fixed set of kFullWaves waves takes tiles of 64 x
-// kFullIPT nonzeros in a fixed order (wave w: tiles w, w + kFullWaves, ...),
+// kFullIPT nonzeros in a fixed order (wave w: tiles w, w + kFullWaves, ...);
+// the vectors that fit are staged in each block's LDS;
 // every lane sums its products in order (FP64; the compensated form keeps
 // exact FP32 product pairs and Dot2 sums), the wave adds its lanes with a
 // fixed butterfly in FP64, and one block adds the kFullWaves wave sums with a
@@ -22,9 +23,12 @@
 namespace ttv {
 namespace {
 
-constexpr int kFullThreads = 256;  // 4 waves
-constexpr int kFullBlocks = 2048;
-constexpr int kFullWaves = kFullBlocks * kFullThreads / 64;  // wave sums (8192)
+constexpr int kFullWaves = 8192;               // wave sums: fixed, whatever the block shape
+// threads per block: 16 waves for narrow rows (room for staged vectors), 4
+// for wide ones (their registers)
+template <int MO>
+constexpr int full_threads() { return MO <= 3 ? 1024 : 256; }
+constexpr size_t kFullLdsBudget = 128 * 1024;                // LDS per block: row stage + staged vectors
 constexpr int kFullIPT = 4;                                  // nonzeros per lane per tile
 constexpr int kFullCombine = 1024;                           // threads of the final sum
 constexpr size_t kFullHdr = 256;                             // error word at Ctrl's offset
@@ -40,18 +44,44 @@ struct FullArgs {
   int validate;
   int32_t* err;
   double* partials;  // kFullWaves wave sums
+  long long lds_off[kMaxOrder];  // byte offset of a vector staged in LDS, -1 if read from global memory
 };
 
 template <typename IdxT, int F, int MO>
-__global__ __launch_bounds__(kFullThreads) void k_full(FullArgs A) {
+__global__ __launch_bounds__(full_threads<MO>()) void k_full(FullArgs A) {
+  constexpr int kFullThreads = full_threads<MO>();
   using FO = FormOps<F>;
   using Acc = typename FO::Acc;
   using In = typename FO::In;
   constexpr int IPT = kFullIPT;
   constexpr long long T = 64LL * IPT;
   __shared__ IdxT stage[kFullThreads / 64][64 * MO];
+  extern __shared__ __attribute__((aligned(16))) unsigned char vsm[];  // staged vectors
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const unsigned ln = lane_id();
+  // the vectors that fit in LDS, copied once per block (16 loads per thread
+  // issued together, then their stores): a gather from LDS instead of a
+  // cache line from L2 per lane
+  for (int m = 0; m < (MO <= 3 ? MO : 0); ++m) {
+    if (m >= A.order || A.lds_off[m] < 0) continue;
+    In* vs = reinterpret_cast<In*>(vsm + A.lds_off[m]);
+    const gptr<const In> gv = to_global(static_cast<const In*>(A.vec[m]));
+    const long long len = A.dims[m];
+    for (long long b = 0; b < len; b += 16LL * kFullThreads) {
+      In t[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const long long i = b + (long long)q * kFullThreads + threadIdx.x;
+        t[q] = i < len ? gv[i] : (In)0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const long long i = b + (long long)q * kFullThreads + threadIdx.x;
+        if (i < len) vs[i] = t[q];
+      }
+    }
+  }
+  __syncthreads();
   const long long gw = (long long)blockIdx.x * (kFullThreads / 64) + w;
   const gptr<const In> vals = to_global(static_cast<const In*>(A.vals));
   const bool rowmajor = rows_coalesced(A.order, A.se, A.sj);
@@ -76,7 +106,10 @@ __global__ __launch_bounds__(kFullThreads) void k_full(FullArgs A) {
                                 atomicCAS(A.err, 0, TTV_E_INDEX);
                                 x = 0;
                               }
-                              g[m][j] = to_global(static_cast<const In*>(A.vec[m]))[x];
+                              if (MO <= 3 && A.lds_off[m] >= 0)
+                                g[m][j] = reinterpret_cast<const In*>(vsm + A.lds_off[m])[x];
+                              else
+                                g[m][j] = to_global(static_cast<const In*>(A.vec[m]))[x];
                             });
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -134,14 +167,45 @@ int check_full(const ttv_coo_desc* X, int& form, int& idx64) {
   return TTV_OK;
 }
 
+// Stages in LDS, in mode order, every vector that still fits in the budget
+// left by the kernel's row stage; returns the dynamic LDS bytes.
+size_t plan_staging(FullArgs& A, int order, size_t vsz, size_t stage_bytes) {
+  size_t used = 0;
+  for (int m = 0; m < kMaxOrder; ++m) {
+    A.lds_off[m] = -1;
+    if (m >= order) continue;
+    const size_t b = ((size_t)A.dims[m] * vsz + 15) & ~(size_t)15;
+    if (stage_bytes + used + b <= kFullLdsBudget) {
+      A.lds_off[m] = (long long)used;
+      used += b;
+    }
+  }
+  return used;
+}
+
+template <typename IdxT, int F, int MO>
+void launch_full_k(FullArgs A, int order, hipStream_t s) {
+  using In = typename FormOps<F>::In;
+  constexpr int NT = full_threads<MO>();
+  size_t lds = 0;
+  if (MO <= 3) {
+    lds = plan_staging(A, order, sizeof(In), sizeof(IdxT) * (NT / 64) * 64 * MO);
+  } else {
+    for (int m = 0; m < kMaxOrder; ++m) A.lds_off[m] = -1;
+  }
+  if (lds > 0)
+    hipFuncSetAttribute((const void*)k_full<IdxT, F, MO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_full<IdxT, F, MO>), dim3(kFullWaves * 64 / NT), dim3(NT), lds, s, A);
+}
+
 template <typename IdxT, int F>
-void launch_full_mo(const FullArgs& A, int mo, hipStream_t s) {
+void launch_full_mo(const FullArgs& A, int mo, int order, hipStream_t s) {
   if (mo <= 3)
-    hipLaunchKernelGGL((k_full<IdxT, F, 3>), dim3(kFullBlocks), dim3(kFullThreads), 0, s, A);
+    launch_full_k<IdxT, F, 3>(A, order, s);
   else if (mo <= 5)
-    hipLaunchKernelGGL((k_full<IdxT, F, 5>), dim3(kFullBlocks), dim3(kFullThreads), 0, s, A);
+    launch_full_k<IdxT, F, 5>(A, order, s);
   else
-    hipLaunchKernelGGL((k_full<IdxT, F, kMaxOrder>), dim3(kFullBlocks), dim3(kFullThreads), 0, s, A);
+    launch_full_k<IdxT, F, kMaxOrder>(A, order, s);
 }
 
 }  // namespace
@@ -194,14 +258,14 @@ int ttv_coo_full(const ttv_coo_desc* X, const void* const* vecs, const int64_t* 
   prof_begin(TTV_PROF_FULL, s);
   if (idx64) {
     if (form == kF64)
-      launch_full_mo<long long, kF64>(A, mo, s);
+      launch_full_mo<long long, kF64>(A, mo, X->order, s);
     else
-      launch_full_mo<long long, kC32>(A, mo, s);
+      launch_full_mo<long long, kC32>(A, mo, X->order, s);
   } else {
     if (form == kF64)
-      launch_full_mo<int, kF64>(A, mo, s);
+      launch_full_mo<int, kF64>(A, mo, X->order, s);
     else
-      launch_full_mo<int, kC32>(A, mo, s);
+      launch_full_mo<int, kC32>(A, mo, X->order, s);
   }
   prof_end(TTV_PROF_FULL, s);
   hipLaunchKernelGGL(k_full_combine, dim3(1), dim3(kFullCombine), 0, s, A.partials, y, out_f64);
