@@ -11,11 +11,11 @@
 // through the segment map.  The optional per-nonzero output is the product of
 // all factors (the gradient with respect to vals).
 //
-// Accumulation is atomics-free and deterministic: a block takes tiles of
-// nonzeros in a fixed order, sorts each tile by key in LDS (stable radix
-// sort), reduces every run of equal keys with a segmented scan and adds the
-// run's sum into its private dense LDS partial (one writer per key).  The
-// blocks' partials are summed in a fixed block order in FP64.
+// Accumulation is free of global atomics and deterministic: a block takes
+// tiles of nonzeros in a fixed order and adds every product into its private
+// dense LDS partial in FP64 (for FP32 inputs, the exact FP32 product pair
+// widened to FP64), in nonzero order; the blocks' partials are summed in a
+// fixed block order in FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,28 +32,18 @@ constexpr int NT = kDenseThreads;
 constexpr int NW = NT / 64;
 constexpr int IPT = kDenseIPT;
 constexpr int TA = NT * IPT;  // nonzeros per tile
-constexpr int MAXD = 8;       // LDS digit bits
 
 template <typename IdxT, int F, int MO, int NACC>
 __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
   using FO = FormOps<F>;
-  using Acc = typename FO::Acc;
   using In = typename FO::In;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // layout: accumulators | row stage IdxT[NW][64*MO] | (sort form only) keys u32[TA] | idx u16[TA] |
-  //         pay u64[TA] | cnt u32[NW<<MAXD]
-  Acc* accs = reinterpret_cast<Acc*>(smem);
+  // layout: FP64 accumulators | row stage IdxT[NW][64*MO]
+  double* accs = reinterpret_cast<double*>(smem);
   IdxT* stage = reinterpret_cast<IdxT*>(smem + A.acc_bytes);
-  unsigned char* sortb = smem + A.acc_bytes + (size_t)NW * 64 * MO * sizeof(IdxT);
-  unsigned* sk = reinterpret_cast<unsigned*>(sortb);
-  unsigned short* si = reinterpret_cast<unsigned short*>(sk + TA);
-  uint64_t* sp = reinterpret_cast<uint64_t*>(sortb + TA * 4 + TA * 2);
-  unsigned* cnt = reinterpret_cast<unsigned*>(sp + TA);
-  __shared__ unsigned wsum[NW];
-  __shared__ Seg<F> wagg[NW];
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
-  for (int i = tid; i < A.acc_total; i += NT) accs[i] = FO::zero();
+  for (int i = tid; i < A.acc_total; i += NT) accs[i] = 0.0;
   __syncthreads();
   const gptr<const In> vals = to_global(static_cast<const In*>(A.vals));
   const bool rowmajor = rows_coalesced(A.order, A.se, A.sj[1]);
@@ -159,168 +149,30 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) pay[q][j] = pa[q][j];
     }
-    if constexpr (F == kF64) {
-      // ---- FP64: LDS atomic adds in nonzero order.  Waves take turns; in a
-      // wave, items in order, and the lanes of one ds_add_f64 that hit the
-      // same entry are applied in ascending lane order (as for the integer
-      // adds the stable ranks rely on).  The block's partial is therefore
-      // the in-order sum of its tiles, bitwise repeatable. ----
-#pragma unroll
-      for (int q = 0; q < NACC; ++q) {
-        if (q >= A.nacc) break;
-        Acc* acc = accs + A.acc_off[q];
-        for (int turn = 0; turn < NW; ++turn) {
-          if (w == turn) {
-#pragma unroll
-            for (int j = 0; j < IPT; ++j)
-              if (w * 64 * IPT + j * 64 + (int)ln < n) atomicAdd(&acc[key[q][j]], FO::from_pay(pay[q][j]));
-          }
-          __syncthreads();
-        }
-      }
-      continue;
-    }
-    // ---- per accumulator: stable LDS radix sort by key, segmented reduce ----
+    // ---- LDS atomic adds in FP64, in nonzero order.  Waves take turns; in
+    // a wave, items in order, and the lanes of one ds_add_f64 that hit the
+    // same entry are applied in ascending lane order (as for the integer
+    // adds the stable ranks rely on).  The block's partial is therefore the
+    // in-order sum of its tiles, bitwise repeatable.  FP32 inputs add their
+    // exact product pair widened to FP64 (no rounding before the sum). ----
 #pragma unroll
     for (int q = 0; q < NACC; ++q) {
       if (q >= A.nacc) break;
-      Acc* acc = accs + A.acc_off[q];
-      const int bits = A.key_bits[q];
-      unsigned k[IPT];
-      unsigned ix[IPT];
+      double* acc = accs + A.acc_off[q];
+      for (int turn = 0; turn < NW; ++turn) {
+        if (w == turn) {
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const int i = w * 64 * IPT + j * 64 + (int)ln;
-        k[j] = key[q][j];
-        ix[j] = (unsigned)i;
-        if (i < n) sp[i] = pay[q][j];
-      }
-      const int npass = (bits + MAXD - 1) / MAXD;
-      const int dw = npass ? (bits + npass - 1) / npass : 0;
-      const int nb = 1 << dw;
-      const unsigned dmask = (unsigned)nb - 1u;
-      for (int pass = 0; pass < npass; ++pass) {
-        const int sh = pass * dw;
-        for (int c = tid; c < NW * nb; c += NT) cnt[c] = 0u;
-        __syncthreads();
-        unsigned rk[IPT];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          rk[j] = 0;
-          // stable rank: same-address lanes of one LDS atomic are served in lane order
-          if (i < n) rk[j] = atomicAdd(&cnt[w * nb + ((k[j] >> sh) & dmask)], 1u);
-        }
-        __syncthreads();
-        {
-          const int E = NW * nb;
-          const int ept = (E + NT - 1) / NT;
-          unsigned v[4], s = 0;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int e = tid * ept + c;
-            v[c] = (c < ept && e < E) ? cnt[(e % NW) * nb + e / NW] : 0u;
-            s += v[c];
-          }
-          unsigned tot;
-          unsigned ex = block_excl_scan<NT>(s, wsum, tot);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int e = tid * ept + c;
-            if (c < ept && e < E) cnt[(e % NW) * nb + e / NW] = ex;
-            ex += v[c];
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          if (i < n) {
-            const unsigned dest = cnt[w * nb + ((k[j] >> sh) & dmask)] + rk[j];
-            if (dest < (unsigned)n) {  // always, unless the counters are corrupt: then report, never write outside
-              sk[dest] = k[j];
-              si[dest] = (unsigned short)ix[j];
-            } else {
-              atomicCAS(A.err, 0, TTV_E_DEVICE);
-            }
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          if (i < n) {
-            k[j] = sk[i];
-            ix[j] = si[i];
-          }
+          for (int j = 0; j < IPT; ++j)
+            if (w * 64 * IPT + j * 64 + (int)ln < n) atomicAdd(&acc[key[q][j]], FO::to_f64(FO::from_pay(pay[q][j])));
         }
         __syncthreads();
       }
-      // k[], ix[] now hold the sorted order in the same (wave, item, lane)
-      // positions.  Segmented scan in rounds of 64 consecutive positions.
-      uint64_t hm[IPT];
-      Acc val[IPT];
-      // heads need the previous position's key: read the sorted keys back
-      if (npass == 0) {
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          if (i < n) sk[i] = k[j];
-        }
-        __syncthreads();
-      }
-      {
-        Acc c = FO::zero();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const int i = w * 64 * IPT + j * 64 + (int)ln;
-          const bool hd = i < n && (i == 0 || sk[i - 1] != k[j]);
-          hm[j] = ballot(hd);
-          Seg<F> e;
-          e.f = hd ? 1 : 0;
-          e.v = i < n ? FO::from_pay(sp[ix[j]]) : FO::zero();
-          e = wave_seg_scan<F>(e);
-          val[j] = e.f ? e.v : FO::add(c, e.v);
-          c = FO::shfl_last(val[j]);
-        }
-        if (ln == 0) {
-          bool any = false;
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) any = any || hm[j] != 0;
-          wagg[w].f = any ? 1 : 0;
-          wagg[w].v = c;
-        }
-      }
-      __syncthreads();
-      {
-        Seg<F> cw;
-        cw.f = 0;
-        cw.v = FO::zero();
-        for (int r = 0; r < w; ++r) cw = seg_combine<F>(cw, wagg[r]);
-        bool lead = true;
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const uint64_t upto = hm[j] & (~0ull >> (63 - ln));
-          if (lead && upto == 0) val[j] = FO::add(cw.v, val[j]);
-          lead = lead && hm[j] == 0;
-        }
-      }
-      // segment ends add their run into the block's dense partial
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const int i = w * 64 * IPT + j * 64 + (int)ln;
-        if (i < n) {
-          const bool end = (i == n - 1) || sk[i + 1] != k[j];
-          if (end) acc[k[j]] = FO::add(acc[k[j]], val[j]);
-        }
-      }
-      __syncthreads();
     }
   }
   __syncthreads();
   // block partials, FP64
   for (int i = tid; i < A.acc_total; i += NT)
-    to_global(A.partials)[(size_t)blockIdx.x * A.acc_total + i] = FO::to_f64(accs[i]);
+    to_global(A.partials)[(size_t)blockIdx.x * A.acc_total + i] = accs[i];
 }
 
 // Sum the block partials of every output entry in block order (FP64).
@@ -404,9 +256,8 @@ int launch_dense_impl(const DenseArgs& A, int grid, size_t lds, hipStream_t s) {
 }  // namespace
 
 size_t dense_tile_lds(int form, int idx64, int mo) {
-  const size_t stage = (size_t)NW * 64 * mo * (idx64 ? 8 : 4);
-  const size_t sort = form == kF64 ? 0 : (size_t)TA * (4 + 2 + 8) + (size_t)(NW << MAXD) * 4;
-  return stage + sort;
+  (void)form;
+  return (size_t)NW * 64 * mo * (idx64 ? 8 : 4);
 }
 
 template <typename IdxT, int F>
