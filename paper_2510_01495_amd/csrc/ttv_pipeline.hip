@@ -1235,13 +1235,15 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         const int jp = r - 1 - (int)ln;
         lb_early = jp >= 0 ? __hip_atomic_load(&S[jp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagInc;
       }
-      if constexpr (F == kF64 && PM == kPipeTTV) {
+      if constexpr (PM == kPipeTTV) {
         if (keep_pre) {
-          // ---- sort-free FP64 leaf: every record knows its output row (the
-          // rank of its key); each row's sum is built at the position of its
-          // first record, the others adding in leaf order (waves in turn,
-          // items in order, same-entry lanes of one ds_add_f64 in lane
-          // order), so the sum is the in-order sum, bitwise repeatable. ----
+          // ---- sort-free leaf: every record knows its output row (the rank
+          // of its key); each row's sum is built in FP64 at the position of
+          // its first record, the others adding in leaf order (waves in
+          // turn, items in order, same-entry lanes of one ds_add_f64 in lane
+          // order), so the sum is the in-order sum, bitwise repeatable.  An
+          // FP32 record's payload is its exact product pair, widened to FP64
+          // (no rounding before the sum). ----
           unsigned* firstpos = sk;  // per row: leaf position of its first record
           unsigned short* rkey = si;  // per row: its relative key (bits <= 16 here)
           double* acc = reinterpret_cast<double*>(spay);
@@ -1260,25 +1262,29 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           }
           __syncthreads();
           bool dup[IPT];
+          double pv[IPT];  // the record's product in FP64
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
             const int i = w * 64 * nj + j * 64 + (int)ln;
             dup[j] = false;
+            pv[j] = 0.0;
             if (j < nj && i < n) {
-              if (firstpos[row[j]] == (unsigned)i)
+              pv[j] = FO::to_f64(FO::from_pay(spay[i]));
+              if (firstpos[row[j]] == (unsigned)i) {
                 rkey[row[j]] = (unsigned short)k[j];
-              else
+                if constexpr (F != kF64) acc[i] = pv[j];  // the row's sum starts as its first product
+              } else {
                 dup[j] = true;
+              }
             }
           }
           if (u_early < (unsigned)n) {  // some key repeats: in-order adds
+            if constexpr (F != kF64) __syncthreads();  // the first products are in place
             for (int turn = 0; turn < NW; ++turn) {
               if (w == turn) {
 #pragma unroll
-                for (int j = 0; j < IPT; ++j) {
-                  const int i = w * 64 * nj + j * 64 + (int)ln;
-                  if (dup[j]) atomicAdd(&acc[firstpos[row[j]]], __longlong_as_double((long long)spay[i]));
-                }
+                for (int j = 0; j < IPT; ++j)
+                  if (dup[j]) atomicAdd(&acc[firstpos[row[j]]], pv[j]);
               }
               __syncthreads();
             }
