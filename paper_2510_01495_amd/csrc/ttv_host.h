@@ -54,8 +54,8 @@ int launch_drop_zeros(const void* in_subs, const void* in_vals, const long long*
                       void* out_subs, void* out_vals, long long* out_nnz, int nrem, int idx64, int out_f64,
                       hipStream_t s);
 
-// Small FP64 products in one block and one launch (at most kTinyNnz nonzeros
-// and kTinyKeys distinct keys of the remaining modes).
+// Small products in one block and one launch (at most kTinyNnz nonzeros and
+// kTinyKeys distinct keys of the remaining modes), FP64 sums.
 constexpr long long kTinyNnz = 1 << 15;
 constexpr int kTinyKeys = 8192;
 bool tiny_fits(const PipePlan& P, int flags);

@@ -1,4 +1,4 @@
-// Small FP64 products in one launch.  When a product's nonzeros are few and
+// Small products in one launch.  When a product's nonzeros are few and
 // the remaining dimensions span few keys (the 1e4-nnz 100x80x60 workload:
 // 8000 keys), the sorting pipeline's thirteen launches dominate its time.
 // Here one block computes the whole product: every nonzero's packed key (the
@@ -9,11 +9,13 @@
 // of the output tuples -- with their sums.  Every key's sum adds its products
 // in input order (tiles in order, the block's waves taking turns, a wave's
 // items in order, and the lanes of one LDS atomic that hit the same sum
-// applied in lane order), so results are bitwise repeatable.
+// applied in lane order), so results are bitwise repeatable.  The sums are
+// FP64; FP32 inputs add their exact product pair widened to FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstddef>
+#include <type_traits>
 
 #include "ttv_device.hpp"
 #include "ttv_host.h"
@@ -24,8 +26,10 @@ namespace {
 constexpr int kTinyThreads = 1024;
 constexpr int kTinyKeysPerThread = kTinyKeys / kTinyThreads;
 
-template <typename IdxT, int MO>
+template <typename IdxT, int F, int MO>
 __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range, int32_t* err) {
+  using FO = FormOps<F>;
+  using In = typename FO::In;
   constexpr int NW = kTinyThreads / 64;
   constexpr int IPT = MO <= 5 ? 4 : 2;  // nonzeros per lane per tile
   __shared__ double acc[kTinyKeys];
@@ -38,18 +42,18 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
   for (int i = tid; i < kTinyKeys; i += kTinyThreads) acc[i] = 0.0;
   for (int i = tid; i < kTinyKeys / 32; i += kTinyThreads) pres[i] = 0u;
   __syncthreads();
-  const gptr<const double> vals = to_global(static_cast<const double*>(D.vals));
+  const gptr<const In> vals = to_global(static_cast<const In*>(D.vals));
   const bool rowmajor = rows_coalesced(D.order, D.stride_e, D.stride_j);
   constexpr long long TA = (long long)kTinyThreads * IPT;
   for (long long e0 = 0; e0 < D.nnz; e0 += TA) {
     const long long s0 = e0 + (long long)w * 64 * IPT;  // this wave's slice
     const long long n = D.nnz - s0;
     unsigned long long key[IPT];
-    double p[IPT];
+    uint64_t p[IPT];  // product payload (FP64, or the FP32 pair)
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       key[j] = 0;
-      p[j] = (long long)j * 64 + ln < n ? vals[s0 + j * 64 + ln] : 0.0;
+      p[j] = FO::start_prod((long long)j * 64 + ln < n ? vals[s0 + j * 64 + ln] : (In)0);
     }
     for_rows<IdxT, IPT, MO>(static_cast<const IdxT*>(D.subs), D.stride_e, D.stride_j, D.order, rowmajor, s0, n,
                             stage[w], [&](int m, int j, long long x) {
@@ -61,7 +65,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
                               if (D.mrem[m])
                                 key[j] += (unsigned long long)x * D.mstride[m];
                               else if (D.vec[m])
-                                p[j] *= to_global(static_cast<const double*>(D.vec[m]))[x];
+                                p[j] = FO::mul_prod(p[j], to_global(static_cast<const In*>(D.vec[m]))[x]);
                             });
     // the waves take turns adding to the sums (input order per key)
     for (int turn = 0; turn < NW; ++turn) {
@@ -70,7 +74,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
         for (int j = 0; j < IPT; ++j) {
           if ((long long)j * 64 + ln < n) {
             const unsigned k = (unsigned)key[j];
-            atomicAdd(&acc[k], p[j]);
+            atomicAdd(&acc[k], FO::to_f64(FO::from_pay(p[j])));
             atomicOr(&pres[k >> 5], 1u << (k & 31));
           }
         }
@@ -90,11 +94,14 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
   unsigned total;
   unsigned pos = block_excl_scan<kTinyThreads>(c, wsum, total);
   const gptr<IdxT> osubs = to_global(static_cast<IdxT*>(D.out_subs));
-  const gptr<double> ovals = to_global(static_cast<double*>(D.out_vals));
+  const bool of64 = F == kF64 || D.out_f64;
   for (int q = 0; q < kTinyKeysPerThread; ++q) {
     const int k = k0 + q;
     if (k < range && ((pres[k >> 5] >> (k & 31)) & 1u)) {
-      ovals[pos] = acc[k];
+      if (of64)
+        to_global(static_cast<double*>(D.out_vals))[pos] = acc[k];
+      else
+        to_global(static_cast<float*>(D.out_vals))[pos] = (float)acc[k];
       for (int i = 0; i < D.nrem; ++i)
         osubs[(long long)pos * D.nrem + i] =
             (IdxT)(((unsigned long long)k / D.kstride[i]) % (unsigned long long)D.dims[D.rem[i]]);
@@ -107,7 +114,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
 }  // namespace
 
 bool tiny_fits(const PipePlan& P, int flags) {
-  if (P.form != kF64 || (flags & TTV_DROP_ZEROS) || P.d0.nnz > kTinyNnz) return false;
+  if ((flags & TTV_DROP_ZEROS) || P.d0.nnz > kTinyNnz) return false;
   unsigned __int128 range = 1;
   for (int i = 0; i < P.d0.nrem; ++i) range *= (unsigned __int128)P.d0.dims[P.d0.rem[i]];
   return range <= (unsigned __int128)kTinyKeys;
@@ -119,19 +126,26 @@ int launch_tiny(const PipePlan& P, void* ws, hipStream_t s) {
   for (int i = 0; i < P.d0.nrem; ++i) range *= P.d0.dims[P.d0.rem[i]];
   int32_t* err = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + offsetof(Ctrl, error));
   const int mo = row_width_class(P.d0.order, P.d0.stride_e, P.d0.stride_j);
-  auto go = [&](auto idx_tag) {
+  auto go = [&](auto idx_tag, auto form_tag) {
     using IdxT = decltype(idx_tag);
+    constexpr int F = decltype(form_tag)::value;
     if (mo <= 3)
-      hipLaunchKernelGGL((k_tiny<IdxT, 3>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+      hipLaunchKernelGGL((k_tiny<IdxT, F, 3>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
     else if (mo <= 5)
-      hipLaunchKernelGGL((k_tiny<IdxT, 5>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+      hipLaunchKernelGGL((k_tiny<IdxT, F, 5>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
     else
-      hipLaunchKernelGGL((k_tiny<IdxT, kMaxOrder>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+      hipLaunchKernelGGL((k_tiny<IdxT, F, kMaxOrder>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+  };
+  auto by_form = [&](auto idx_tag) {
+    if (P.form == kF64)
+      go(idx_tag, std::integral_constant<int, kF64>());
+    else
+      go(idx_tag, std::integral_constant<int, kC32>());
   };
   if (P.idx64)
-    go((long long)0);
+    by_form((long long)0);
   else
-    go((int)0);
+    by_form((int)0);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_last_hip_error((int)e);

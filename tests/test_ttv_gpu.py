@@ -290,24 +290,30 @@ def test_zipf_c32_repeated_launches():
 @pytest.mark.parametrize("nnz,shape", [(32768, (64, 50, 128)), (32769, (64, 50, 128)), (1, (3, 4, 5)),
                                        (5000, (2, 3, 4, 5, 6, 2, 2, 3))])
 @pytest.mark.parametrize("soa", [False, True])
-def test_small_fp64_one_block_and_pipeline(nnz, shape, soa):
-    """FP64 products of at most 32768 nonzeros whose remaining modes span at
-    most 8192 keys run in one block (dense LDS sums by key); one nonzero more
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_small_one_block_and_pipeline(nnz, shape, soa, dtype):
+    """Products of at most 32768 nonzeros whose remaining modes span at most
+    8192 keys run in one block (dense FP64 LDS sums by key); one nonzero more
     runs the sorting pipeline.  Both against the oracle, at the edges: exactly
     8192 keys (64 x 128), 32768 / 32769 nonzeros, one nonzero, order 8;
-    row-major and column-major subs."""
+    row-major and column-major subs; FP64 and FP32 (FP32 and FP64 output)."""
     P = _api()
     rng = np.random.default_rng(nnz + len(shape))
     mode = 1
     subs_np = np.column_stack([rng.integers(0, s, nnz) for s in shape]).astype(np.int64).reshape(nnz, len(shape))
-    X = synth.COO(subs_np, rng.standard_normal(nnz), shape)
-    v_np = rng.standard_normal(shape[mode])
+    X = synth.COO(subs_np, rng.standard_normal(nnz).astype(dtype), shape)
+    v_np = rng.standard_normal(shape[mode]).astype(dtype)
     subs, vals, v = to_gpu(X, v_np, soa=soa)
-    say(f"small fp64 nnz={nnz} d={len(shape)} soa={soa}")
-    gs, gv, _ = P.ttv(subs, vals, shape, mode, v)
-    check_ttv(X, mode, v_np, gs, gv, F64_TOL, f"small nnz={nnz}")
-    gs2, gv2, _ = P.ttv(subs, vals, shape, mode, v)
+    say(f"small nnz={nnz} d={len(shape)} soa={soa} {np.dtype(dtype).name}")
+    tol = F64_TOL if dtype == np.float64 else C32_TOL
+    gs, gv, _ = P.ttv(subs, vals, shape, mode, v, out_f64=True)
+    check_ttv(X, mode, v_np, gs, gv, tol, f"small nnz={nnz}")
+    gs2, gv2, _ = P.ttv(subs, vals, shape, mode, v, out_f64=True)
     assert np.array_equal(gv.cpu().numpy(), gv2.cpu().numpy()), "not bitwise repeatable"
+    if dtype == np.float32:  # FP32 output: the FP64 result rounded once
+        gs3, gv3, _ = P.ttv(subs, vals, shape, mode, v)
+        assert gv3.dtype == __import__("torch").float32
+        assert np.array_equal(gv3.cpu().numpy(), gv.cpu().numpy().astype(np.float32))
 
 
 @pytest.mark.parametrize("nnz,shape", [(3000, (20, 30, 40)), (60_000, (300, 200, 100))])
