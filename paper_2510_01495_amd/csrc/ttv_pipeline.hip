@@ -259,7 +259,6 @@ __global__ __launch_bounds__(256) void k_init(WsView W, TDesc d0, const TDesc* d
   __syncthreads();
   for (int t = threadIdx.x; t < count; t += blockDim.x)
     if (D[t].out_nnz) *D[t].out_nnz = 0;
-  __shared__ int s_nj;
   if (threadIdx.x == 0) {
     for (int l = 0; l <= kMaxLevels; ++l) {
       C->njobs[l] = 0;
@@ -270,39 +269,76 @@ __global__ __launch_bounds__(256) void k_init(WsView W, TDesc d0, const TDesc* d
     C->ticket = 0;
     C->bm_done = 0;
     C->error = 0;
-    long long tile = 0, total = 0;
-    int nj = 0;
-    Job* J1 = W.jobs(1);
-    for (int t = 0; t < count; ++t) {
-      total += D[t].nnz;
-      if (D[t].nnz == 0) continue;
+  }
+  // level-1 jobs (one per nonempty tensor) and their tiles, in tensor order:
+  // job and first-tile offsets from block scans over chunks of 256 tensors
+  __shared__ unsigned wsum[256 / 64];
+  __shared__ unsigned s_tex[256 + 1];  // first tile of every tensor of the chunk (chunk-relative)
+  __shared__ int s_job[256];           // its job (-1: empty tensor)
+  __shared__ long long s_tile;
+  __shared__ int s_nj;
+  __shared__ unsigned long long s_total;
+  if (threadIdx.x == 0) {
+    s_tile = 0;
+    s_nj = 0;
+    s_total = 0;
+  }
+  __syncthreads();
+  Job* J1 = W.jobs(1);
+  for (int c0 = 0; c0 < count; c0 += 256) {
+    const int t = c0 + (int)threadIdx.x;
+    const long long nnz = t < count ? D[t].nnz : 0;
+    const bool ok = nnz > 0;
+    const unsigned nt = ok ? (unsigned)((nnz + T1 - 1) / T1) : 0u;
+    unsigned ntot, jtot;
+    const unsigned tex = block_excl_scan<256>(nt, wsum, ntot);
+    const unsigned jex = block_excl_scan<256>(ok ? 1u : 0u, wsum, jtot);
+    if (nnz > 0) atomicAdd(&s_total, (unsigned long long)nnz);
+    if (ok) {
       Job J;
       J.start = D[t].base;
-      J.size = D[t].nnz;
+      J.size = nnz;
       J.prefix = 0;
-      J.tile0 = tile;
-      J.ntiles = (int)((D[t].nnz + T1 - 1) / T1);
+      J.tile0 = s_tile + tex;
+      J.ntiles = (int)nt;
       J.tensor = t;
       J.shift = D[t].keybits - D[t].r1;
       J.r = D[t].r1;
       J.src = kSrcRaw;
       J.pad = 0;
-      J1[nj++] = J;
-      tile += J.ntiles;
+      J1[s_nj + (int)jex] = J;
     }
-    C->njobs[1] = nj;
-    C->ntiles[1] = (int)tile;
-    C->total = total;
-    s_nj = nj;
+    s_tex[threadIdx.x] = tex;
+    s_job[threadIdx.x] = ok ? s_nj + (int)jex : -1;
+    if (threadIdx.x == 0) s_tex[256] = ntot;
+    __syncthreads();
+    // the chunk's tiles, one per thread: its tensor by binary search on the
+    // first tiles (empty tensors own no tile)
+    int* T = W.tiles(1);
+    for (unsigned k = threadIdx.x; k < ntot; k += 256) {
+      int lo = 0, hi = 255;  // last tensor whose first tile is <= k and that owns tiles
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_tex[mid] <= k)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      // (the largest such tensor owns tile k: an empty one would share its
+      // first tile with the next, so it cannot be the largest)
+      T[s_tile + k] = s_job[lo];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_tile += ntot;
+      s_nj += (int)jtot;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int nj = s_nj;
-  const Job* J1 = W.jobs(1);
-  int* T = W.tiles(1);
-  for (int j = 0; j < nj; ++j) {
-    const long long t0 = J1[j].tile0;
-    const int nt = J1[j].ntiles;
-    for (int k = threadIdx.x; k < nt; k += blockDim.x) T[t0 + k] = j;
+  if (threadIdx.x == 0) {
+    C->njobs[1] = s_nj;
+    C->ntiles[1] = (int)s_tile;
+    C->total = (long long)s_total;
   }
 }
 
