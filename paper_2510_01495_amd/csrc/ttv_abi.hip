@@ -299,6 +299,7 @@ int ttv_coo_multi_workspace(const ttv_coo_desc* X, int32_t ncon, const int32_t* 
   const int rc = plan_single(X, ncon, modes, flags, kPipeTTV, P);
   if (rc) return rc;
   *bytes = P.L.end;
+  if (keyed_fits(P, flags)) *bytes = std::max(*bytes, keyed_ws(P));
   if (flags & TTV_DROP_ZEROS)
     *bytes = ((P.L.end + 255) & ~(size_t)255) + drop_zeros_ws(X->nnz, P.d0.nrem, P.idx64, out_is_f64(P, flags));
   return TTV_OK;
@@ -324,7 +325,8 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, con
   const bool drop = (flags & TTV_DROP_ZEROS) != 0;
   const size_t tmp_off = (P.L.end + 255) & ~(size_t)255;
   const int of64 = out_is_f64(P, flags);
-  const size_t need = drop ? tmp_off + drop_zeros_ws(X->nnz, P.d0.nrem, P.idx64, of64) : P.L.end;
+  size_t need = drop ? tmp_off + drop_zeros_ws(X->nnz, P.d0.nrem, P.idx64, of64) : P.L.end;
+  if (keyed_fits(P, flags)) need = std::max(need, keyed_ws(P));
   if (!ws || ws_bytes < need) return TTV_E_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   P.cus = device_cus();
@@ -333,6 +335,7 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, con
     P.d0.out_vals = out_vals;
     P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
     if (tiny_fits(P, flags)) return launch_tiny(P, ws, s);
+    if (keyed_fits(P, flags)) return launch_keyed(P, ws, s);
     return launch_pipeline(P, ws, s);
   }
   // the product into the temporary area, then its rows with nonzero sums

@@ -60,6 +60,11 @@ constexpr long long kTinyNnz = 1 << 15;
 constexpr int kTinyKeys = 8192;
 bool tiny_fits(const PipePlan& P, int flags);
 int launch_tiny(const PipePlan& P, void* ws, hipStream_t s);
+// Larger products with at most kTinyKeys keys: per-block dense sums by key,
+// added in block order.
+bool keyed_fits(const PipePlan& P, int flags);
+size_t keyed_ws(const PipePlan& P);
+int launch_keyed(const PipePlan& P, void* ws, hipStream_t s);
 
 constexpr int kAssumedCUs = 256;  // MI355X; tiling never depends on the device queried at call time
 

@@ -1,4 +1,5 @@
-// Small products in one launch.  When a product's nonzeros are few and
+// Products whose remaining modes span few keys, without a sort.  Small ones
+// in one launch.  When a product's nonzeros are few and
 // the remaining dimensions span few keys (the 1e4-nnz 100x80x60 workload:
 // 8000 keys), the sorting pipeline's thirteen launches dominate its time.
 // Here one block computes the whole product: every nonzero's packed key (the
@@ -111,7 +112,190 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
   if (tid == 0) *to_global(D.out_nnz) = (long long)total;
 }
 
+// ---------------------------------------------------------------------------
+// Larger products whose remaining modes span at most kTinyKeys keys (a large
+// contracted mode: many nonzeros per output row).  The same dense sums by
+// key, per block: a fixed number of blocks take tiles in a fixed order, each
+// adds its products into its own LDS sums (in order, as above) and ORs its
+// presence bits into a global bitmap; the blocks' sums are added per key in
+// block order (FP64), and the present keys written in key order.
+// ---------------------------------------------------------------------------
+constexpr int kKeyedBlocks = 512;  // most blocks: the sum order depends on nnz only
+
+template <typename IdxT, int F, int MO>
+__global__ __launch_bounds__(kTinyThreads) void k_keyed(TDesc D, long long range, int32_t* err, double* partials,
+                                                         unsigned* present) {
+  using FO = FormOps<F>;
+  using In = typename FO::In;
+  constexpr int NW = kTinyThreads / 64;
+  constexpr int IPT = MO <= 5 ? 4 : 2;
+  constexpr long long TA = (long long)kTinyThreads * IPT;
+  __shared__ double acc[kTinyKeys];
+  __shared__ unsigned pres[kTinyKeys / 32];
+  __shared__ IdxT stage[NW][64 * MO];
+  const int tid = threadIdx.x, w = tid >> 6;
+  const unsigned ln = lane_id();
+  for (int i = tid; i < kTinyKeys; i += kTinyThreads) acc[i] = 0.0;
+  for (int i = tid; i < kTinyKeys / 32; i += kTinyThreads) pres[i] = 0u;
+  __syncthreads();
+  const gptr<const In> vals = to_global(static_cast<const In*>(D.vals));
+  const bool rowmajor = rows_coalesced(D.order, D.stride_e, D.stride_j);
+  const long long ntiles = (D.nnz + TA - 1) / TA;
+  for (long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const long long s0 = t * TA + (long long)w * 64 * IPT;  // this wave's slice
+    const long long n = D.nnz - s0;
+    unsigned long long key[IPT];
+    uint64_t p[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      key[j] = 0;
+      p[j] = FO::start_prod((long long)j * 64 + ln < n ? vals[s0 + j * 64 + ln] : (In)0);
+    }
+    for_rows<IdxT, IPT, MO>(static_cast<const IdxT*>(D.subs), D.stride_e, D.stride_j, D.order, rowmajor, s0, n,
+                            stage[w], [&](int m, int j, long long x) {
+                              if ((long long)j * 64 + ln >= n) return;
+                              if (D.validate && (x < 0 || x >= D.dims[m])) {
+                                atomicCAS(err, 0, TTV_E_INDEX);
+                                x = 0;
+                              }
+                              if (D.mrem[m])
+                                key[j] += (unsigned long long)x * D.mstride[m];
+                              else if (D.vec[m])
+                                p[j] = FO::mul_prod(p[j], to_global(static_cast<const In*>(D.vec[m]))[x]);
+                            });
+    for (int turn = 0; turn < NW; ++turn) {
+      if (w == turn) {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          if ((long long)j * 64 + ln < n) {
+            const unsigned k = (unsigned)key[j];
+            atomicAdd(&acc[k], FO::to_f64(FO::from_pay(p[j])));
+            atomicOr(&pres[k >> 5], 1u << (k & 31));
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  const gptr<double> part = to_global(partials) + (size_t)blockIdx.x * range;
+  for (long long i = tid; i < range; i += kTinyThreads) part[i] = acc[i];
+  for (long long i = tid; i < (range + 31) / 32; i += kTinyThreads)
+    if (pres[i]) atomicOr(&present[i], pres[i]);
+}
+
+// Per key: the blocks' sums in block order; then the present keys in key
+// order (one block).
+__global__ __launch_bounds__(256) void k_keyed_sum(const double* partials, int nparts, long long range, double* y) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= range) return;
+  const gptr<const double> part = to_global(partials);
+  double s = 0.0;
+#pragma unroll 8
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * range + k];
+  to_global(y)[k] = s;
+}
+
+template <typename IdxT>
+__global__ __launch_bounds__(kTinyThreads) void k_keyed_write(TDesc D, long long range, const double* y,
+                                                              const unsigned* present) {
+  __shared__ unsigned wsum[kTinyThreads / 64];
+  const int k0 = (int)threadIdx.x * kTinyKeysPerThread;
+  const gptr<const unsigned> pr = to_global(present);
+  unsigned c = 0;
+#pragma unroll
+  for (int q = 0; q < kTinyKeysPerThread; ++q) {
+    const int k = k0 + q;
+    c += (k < range && ((pr[k >> 5] >> (k & 31)) & 1u)) ? 1u : 0u;
+  }
+  unsigned total;
+  unsigned pos = block_excl_scan<kTinyThreads>(c, wsum, total);
+  const gptr<IdxT> osubs = to_global(static_cast<IdxT*>(D.out_subs));
+  const bool of64 = D.out_f64 != 0;  // FP64 values (FP64 inputs or TTV_OUT_F64), set by the launcher
+  for (int q = 0; q < kTinyKeysPerThread; ++q) {
+    const int k = k0 + q;
+    if (k < range && ((pr[k >> 5] >> (k & 31)) & 1u)) {
+      const double v = to_global(y)[k];
+      if (of64)
+        to_global(static_cast<double*>(D.out_vals))[pos] = v;
+      else
+        to_global(static_cast<float*>(D.out_vals))[pos] = (float)v;
+      for (int i = 0; i < D.nrem; ++i)
+        osubs[(long long)pos * D.nrem + i] =
+            (IdxT)(((unsigned long long)k / D.kstride[i]) % (unsigned long long)D.dims[D.rem[i]]);
+      ++pos;
+    }
+  }
+  if (threadIdx.x == 0) *to_global(D.out_nnz) = (long long)total;
+}
+
 }  // namespace
+
+long long keyed_range(const PipePlan& P) {
+  unsigned __int128 range = 1;
+  for (int i = 0; i < P.d0.nrem; ++i) range *= (unsigned __int128)P.d0.dims[P.d0.rem[i]];
+  return range <= (unsigned __int128)kTinyKeys ? (long long)range : -1;
+}
+
+bool keyed_fits(const PipePlan& P, int flags) {
+  return !(flags & TTV_DROP_ZEROS) && P.d0.nnz > kTinyNnz && keyed_range(P) > 0;
+}
+
+static long long keyed_parts(long long nnz) {
+  const long long tiles = (nnz + 4096 - 1) / 4096;
+  return std::max<long long>(1, std::min<long long>(kKeyedBlocks, tiles));
+}
+
+size_t keyed_ws(const PipePlan& P) {
+  const long long range = keyed_range(P);
+  if (range <= 0) return 0;
+  // header (error word) | bitmap | y | partials
+  return 256 + 256 * 8 + (size_t)range * 8 + (size_t)keyed_parts(P.d0.nnz) * range * 8 + 256;
+}
+
+int launch_keyed(const PipePlan& P, void* ws, hipStream_t s) {
+  (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
+  const long long range = keyed_range(P);
+  char* w = static_cast<char*>(ws);
+  int32_t* err = reinterpret_cast<int32_t*>(w + offsetof(Ctrl, error));
+  unsigned* present = reinterpret_cast<unsigned*>(w + 256);
+  double* y = reinterpret_cast<double*>(w + 256 + 256 * 8);
+  double* partials = reinterpret_cast<double*>(w + 256 + 256 * 8 + ((range * 8 + 255) & ~255LL));
+  if (int rc = launch_zero(w, 256 + 256 * 8, s)) return rc;  // error word and bitmap
+  const int G = (int)keyed_parts(P.d0.nnz);
+  TDesc D = P.d0;
+  D.out_f64 = (P.form == kF64 || D.out_f64) ? 1 : 0;
+  const int mo = row_width_class(D.order, D.stride_e, D.stride_j);
+  auto go = [&](auto idx_tag, auto form_tag) {
+    using IdxT = decltype(idx_tag);
+    constexpr int F = decltype(form_tag)::value;
+    if (mo <= 3)
+      hipLaunchKernelGGL((k_keyed<IdxT, F, 3>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials, present);
+    else if (mo <= 5)
+      hipLaunchKernelGGL((k_keyed<IdxT, F, 5>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials, present);
+    else
+      hipLaunchKernelGGL((k_keyed<IdxT, F, kMaxOrder>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials,
+                         present);
+    hipLaunchKernelGGL(k_keyed_sum, dim3((unsigned)((range + 255) / 256)), dim3(256), 0, s, partials, G, range, y);
+    hipLaunchKernelGGL((k_keyed_write<IdxT>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y, present);
+  };
+  auto by_form = [&](auto idx_tag) {
+    if (P.form == kF64)
+      go(idx_tag, std::integral_constant<int, kF64>());
+    else
+      go(idx_tag, std::integral_constant<int, kC32>());
+  };
+  if (P.idx64)
+    by_form((long long)0);
+  else
+    by_form((int)0);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  return TTV_OK;
+}
 
 bool tiny_fits(const PipePlan& P, int flags) {
   if ((flags & TTV_DROP_ZEROS) || P.d0.nnz > kTinyNnz) return false;

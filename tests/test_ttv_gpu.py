@@ -337,3 +337,55 @@ def test_validate_reports_bad_index(nnz, shape):
     op = P.TTVOp(torch.from_numpy(subs_np).cuda(), vals, shape, [1], [v], flags=L.VALIDATE)
     op.launch()
     assert op.device_error() == 0
+
+
+@pytest.mark.parametrize("shape,mode,nnz,idx,val", [
+    ((100, 100_000, 80), 1, 500_000, np.int64, np.float64),
+    ((64, 1000, 128), 1, 100_000, np.int64, np.float64),
+    ((10, 20, 50_000, 30), 2, 300_000, np.int32, np.float32),
+    ((7, 40_000, 3, 2, 5), 1, 200_000, np.int32, np.float64),
+])
+@pytest.mark.parametrize("soa", [False, True])
+def test_few_keys_many_nonzeros(shape, mode, nnz, idx, val, soa):
+    """More than 32768 nonzeros whose remaining modes span at most 8192 keys
+    (a large contracted mode): per-block dense sums by key, added in block
+    order, present keys written in key order.  Against the oracle (FP32 also
+    with FP32 output, rounded once), bitwise repeatable."""
+    P = _api()
+    rng = np.random.default_rng(nnz + mode)
+    subs_np = np.column_stack([rng.integers(0, s, nnz) for s in shape]).astype(idx)
+    X = synth.COO(subs_np, rng.standard_normal(nnz).astype(val), shape)
+    v_np = rng.standard_normal(shape[mode]).astype(val)
+    subs, vals, v = to_gpu(X, v_np, soa=soa)
+    say(f"few keys {shape} mode {mode} nnz {nnz} soa={soa}")
+    tol = F64_TOL if val == np.float64 else C32_TOL
+    gs, gv, _ = P.ttv(subs, vals, shape, mode, v, out_f64=True)
+    check_ttv(X, mode, v_np, gs, gv, tol, "few keys")
+    gs2, gv2, _ = P.ttv(subs, vals, shape, mode, v, out_f64=True)
+    assert np.array_equal(gv.cpu().numpy(), gv2.cpu().numpy()), "not bitwise repeatable"
+    if val == np.float32:
+        _, gv3, _ = P.ttv(subs, vals, shape, mode, v)
+        assert np.array_equal(gv3.cpu().numpy(), gv.cpu().numpy().astype(np.float32))
+
+
+def test_few_keys_integer_exact_and_validate():
+    """Integer data through the per-block dense sums: every order is exact,
+    so equal to the oracle bitwise; an index past its dimension under
+    TTV_VALIDATE records TTV_E_INDEX."""
+    import torch
+    P = _api()
+    from paper_2510_01495_amd import _lib as L
+    rng = np.random.default_rng(77)
+    shape, mode, nnz = (50, 200_000, 100), 1, 400_000
+    subs_np = np.column_stack([rng.integers(0, s, nnz) for s in shape]).astype(np.int64)
+    X = synth.COO(subs_np, rng.integers(-9, 10, nnz).astype(np.float64), shape)
+    v_np = rng.integers(-9, 10, shape[mode]).astype(np.float64)
+    subs, vals, v = to_gpu(X, v_np)
+    gs, gv, _ = P.ttv(subs, vals, shape, mode, v)
+    ns, nv, _ = oracle.ttv(X.subs, X.vals, shape, mode, v_np)
+    assert np.array_equal(gs.cpu().numpy(), ns) and np.array_equal(gv.cpu().numpy(), nv)
+    bad = subs_np.copy()
+    bad[nnz // 3, 2] = shape[2]
+    op = P.TTVOp(torch.from_numpy(bad).cuda(), vals, shape, [mode], [v], flags=L.VALIDATE)
+    op.launch()
+    assert op.device_error() == -8
