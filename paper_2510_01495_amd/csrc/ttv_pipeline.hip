@@ -1272,7 +1272,9 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         lb_early = jp >= 0 ? __hip_atomic_load(&S[jp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagInc;
       }
       if constexpr (PM == kPipeTTV) {
-        if (keep_pre) {
+        // (a leaf of few distinct keys is sorted instead: its in-order adds
+        // would pile many lanes of one atomic onto one row)
+        if (keep_pre && u_early >= 64u) {
           // ---- sort-free leaf: every record knows its output row (the rank
           // of its key); each row's sum is built in FP64 at the position of
           // its first record, the others adding in leaf order (waves in
