@@ -55,7 +55,8 @@ int launch_drop_zeros(const void* in_subs, const void* in_vals, const long long*
                       hipStream_t s);
 
 // Small products in one block and one launch (at most kTinyNnz nonzeros and
-// kTinyKeys distinct keys of the remaining modes), FP64 sums.
+// kTinyKeys keys of the remaining modes -- twice that for rows of at most
+// three indices), FP64 sums.
 constexpr long long kTinyNnz = 1 << 15;
 constexpr int kTinyKeys = 8192;
 bool tiny_fits(const PipePlan& P, int flags);

@@ -25,7 +25,10 @@ namespace ttv {
 namespace {
 
 constexpr int kTinyThreads = 1024;
-constexpr int kTinyKeysPerThread = kTinyKeys / kTinyThreads;
+// keys held in LDS: 16384 FP64 sums (128 KB) beside the row stage of rows of
+// up to 3 indices, 8192 beside the wider ones
+template <int MO>
+constexpr int key_cap() { return MO <= 3 ? 2 * kTinyKeys : kTinyKeys; }
 
 template <typename IdxT, int F, int MO>
 __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range, int32_t* err) {
@@ -33,15 +36,17 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
   using In = typename FO::In;
   constexpr int NW = kTinyThreads / 64;
   constexpr int IPT = MO <= 5 ? 4 : 2;  // nonzeros per lane per tile
-  __shared__ double acc[kTinyKeys];
-  __shared__ unsigned pres[kTinyKeys / 32];
+  constexpr int KC = key_cap<MO>();
+  constexpr int KPT = KC / kTinyThreads;  // keys per thread when writing
+  __shared__ double acc[KC];
+  __shared__ unsigned pres[KC / 32];
   __shared__ IdxT stage[NW][64 * MO];
   __shared__ unsigned wsum[NW];
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
   if (tid == 0) *to_global(err) = 0;
-  for (int i = tid; i < kTinyKeys; i += kTinyThreads) acc[i] = 0.0;
-  for (int i = tid; i < kTinyKeys / 32; i += kTinyThreads) pres[i] = 0u;
+  for (int i = tid; i < KC; i += kTinyThreads) acc[i] = 0.0;
+  for (int i = tid; i < KC / 32; i += kTinyThreads) pres[i] = 0u;
   __syncthreads();
   const gptr<const In> vals = to_global(static_cast<const In*>(D.vals));
   const bool rowmajor = rows_coalesced(D.order, D.stride_e, D.stride_j);
@@ -83,12 +88,11 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
       __syncthreads();
     }
   }
-  // present keys in key order: every thread takes kTinyKeysPerThread
-  // consecutive keys
-  const int k0 = tid * kTinyKeysPerThread;
+  // present keys in key order: every thread takes KPT consecutive keys
+  const int k0 = tid * KPT;
   unsigned c = 0;
 #pragma unroll
-  for (int q = 0; q < kTinyKeysPerThread; ++q) {
+  for (int q = 0; q < KPT; ++q) {
     const int k = k0 + q;
     c += (k < range && ((pres[k >> 5] >> (k & 31)) & 1u)) ? 1u : 0u;
   }
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
   unsigned pos = block_excl_scan<kTinyThreads>(c, wsum, total);
   const gptr<IdxT> osubs = to_global(static_cast<IdxT*>(D.out_subs));
   const bool of64 = F == kF64 || D.out_f64;
-  for (int q = 0; q < kTinyKeysPerThread; ++q) {
+  for (int q = 0; q < KPT; ++q) {
     const int k = k0 + q;
     if (k < range && ((pres[k >> 5] >> (k & 31)) & 1u)) {
       if (of64)
@@ -130,13 +134,14 @@ __global__ __launch_bounds__(kTinyThreads) void k_keyed(TDesc D, long long range
   constexpr int NW = kTinyThreads / 64;
   constexpr int IPT = MO <= 5 ? 4 : 2;
   constexpr long long TA = (long long)kTinyThreads * IPT;
-  __shared__ double acc[kTinyKeys];
-  __shared__ unsigned pres[kTinyKeys / 32];
+  constexpr int KC = key_cap<MO>();
+  __shared__ double acc[KC];
+  __shared__ unsigned pres[KC / 32];
   __shared__ IdxT stage[NW][64 * MO];
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
-  for (int i = tid; i < kTinyKeys; i += kTinyThreads) acc[i] = 0.0;
-  for (int i = tid; i < kTinyKeys / 32; i += kTinyThreads) pres[i] = 0u;
+  for (int i = tid; i < KC; i += kTinyThreads) acc[i] = 0.0;
+  for (int i = tid; i < KC / 32; i += kTinyThreads) pres[i] = 0u;
   __syncthreads();
   const gptr<const In> vals = to_global(static_cast<const In*>(D.vals));
   const bool rowmajor = rows_coalesced(D.order, D.stride_e, D.stride_j);
@@ -196,15 +201,16 @@ __global__ __launch_bounds__(256) void k_keyed_sum(const double* partials, int n
   to_global(y)[k] = s;
 }
 
-template <typename IdxT>
+template <typename IdxT, int KC>
 __global__ __launch_bounds__(kTinyThreads) void k_keyed_write(TDesc D, long long range, const double* y,
                                                               const unsigned* present) {
+  constexpr int KPT = KC / kTinyThreads;
   __shared__ unsigned wsum[kTinyThreads / 64];
-  const int k0 = (int)threadIdx.x * kTinyKeysPerThread;
+  const int k0 = (int)threadIdx.x * KPT;
   const gptr<const unsigned> pr = to_global(present);
   unsigned c = 0;
 #pragma unroll
-  for (int q = 0; q < kTinyKeysPerThread; ++q) {
+  for (int q = 0; q < KPT; ++q) {
     const int k = k0 + q;
     c += (k < range && ((pr[k >> 5] >> (k & 31)) & 1u)) ? 1u : 0u;
   }
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_keyed_write(TDesc D, long long
   unsigned pos = block_excl_scan<kTinyThreads>(c, wsum, total);
   const gptr<IdxT> osubs = to_global(static_cast<IdxT*>(D.out_subs));
   const bool of64 = D.out_f64 != 0;  // FP64 values (FP64 inputs or TTV_OUT_F64), set by the launcher
-  for (int q = 0; q < kTinyKeysPerThread; ++q) {
+  for (int q = 0; q < KPT; ++q) {
     const int k = k0 + q;
     if (k < range && ((pr[k >> 5] >> (k & 31)) & 1u)) {
       const double v = to_global(y)[k];
@@ -231,10 +237,13 @@ __global__ __launch_bounds__(kTinyThreads) void k_keyed_write(TDesc D, long long
 
 }  // namespace
 
+// The product's key count if it fits the LDS sums of its row class, else -1.
 long long keyed_range(const PipePlan& P) {
   unsigned __int128 range = 1;
   for (int i = 0; i < P.d0.nrem; ++i) range *= (unsigned __int128)P.d0.dims[P.d0.rem[i]];
-  return range <= (unsigned __int128)kTinyKeys ? (long long)range : -1;
+  const int mo = row_width_class(P.d0.order, P.d0.stride_e, P.d0.stride_j);
+  const int cap = mo <= 3 ? key_cap<3>() : key_cap<kMaxOrder>();
+  return range <= (unsigned __int128)cap ? (long long)range : -1;
 }
 
 bool keyed_fits(const PipePlan& P, int flags) {
@@ -277,7 +286,11 @@ int launch_keyed(const PipePlan& P, void* ws, hipStream_t s) {
       hipLaunchKernelGGL((k_keyed<IdxT, F, kMaxOrder>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials,
                          present);
     hipLaunchKernelGGL(k_keyed_sum, dim3((unsigned)((range + 255) / 256)), dim3(256), 0, s, partials, G, range, y);
-    hipLaunchKernelGGL((k_keyed_write<IdxT>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y, present);
+    if (mo <= 3)
+      hipLaunchKernelGGL((k_keyed_write<IdxT, key_cap<3>()>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y, present);
+    else
+      hipLaunchKernelGGL((k_keyed_write<IdxT, key_cap<kMaxOrder>()>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y,
+                         present);
   };
   auto by_form = [&](auto idx_tag) {
     if (P.form == kF64)
@@ -298,10 +311,7 @@ int launch_keyed(const PipePlan& P, void* ws, hipStream_t s) {
 }
 
 bool tiny_fits(const PipePlan& P, int flags) {
-  if ((flags & TTV_DROP_ZEROS) || P.d0.nnz > kTinyNnz) return false;
-  unsigned __int128 range = 1;
-  for (int i = 0; i < P.d0.nrem; ++i) range *= (unsigned __int128)P.d0.dims[P.d0.rem[i]];
-  return range <= (unsigned __int128)kTinyKeys;
+  return !(flags & TTV_DROP_ZEROS) && P.d0.nnz <= kTinyNnz && keyed_range(P) >= 0;
 }
 
 int launch_tiny(const PipePlan& P, void* ws, hipStream_t s) {

@@ -288,14 +288,17 @@ def test_zipf_c32_repeated_launches():
 
 
 @pytest.mark.parametrize("nnz,shape", [(32768, (64, 50, 128)), (32769, (64, 50, 128)), (1, (3, 4, 5)),
-                                       (5000, (2, 3, 4, 5, 6, 2, 2, 3))])
+                                       (5000, (2, 3, 4, 5, 6, 2, 2, 3)), (32768, (128, 50, 128)),
+                                       (20000, (129, 50, 128)), (20000, (40, 50, 30, 10))])
 @pytest.mark.parametrize("soa", [False, True])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_small_one_block_and_pipeline(nnz, shape, soa, dtype):
     """Products of at most 32768 nonzeros whose remaining modes span at most
-    8192 keys run in one block (dense FP64 LDS sums by key); one nonzero more
-    runs the sorting pipeline.  Both against the oracle, at the edges: exactly
-    8192 keys (64 x 128), 32768 / 32769 nonzeros, one nonzero, order 8;
+    16384 keys (rows of up to 3 indices; 8192 for wider rows) run in one
+    block (dense FP64 LDS sums by key); one nonzero or key more runs the
+    sorting pipeline.  Both against the oracle, at the edges: 8192 keys
+    (64 x 128) and 16384 keys (128 x 128) at 32768 nonzeros, 32769 nonzeros,
+    16512 keys at order 3, 12000 keys at order 4, one nonzero, order 8;
     row-major and column-major subs; FP64 and FP32 (FP32 and FP64 output)."""
     P = _api()
     rng = np.random.default_rng(nnz + len(shape))
@@ -344,11 +347,13 @@ def test_validate_reports_bad_index(nnz, shape):
     ((64, 1000, 128), 1, 100_000, np.int64, np.float64),
     ((10, 20, 50_000, 30), 2, 300_000, np.int32, np.float32),
     ((7, 40_000, 3, 2, 5), 1, 200_000, np.int32, np.float64),
+    ((120, 100_000, 130), 1, 500_000, np.int64, np.float32),
 ])
 @pytest.mark.parametrize("soa", [False, True])
 def test_few_keys_many_nonzeros(shape, mode, nnz, idx, val, soa):
-    """More than 32768 nonzeros whose remaining modes span at most 8192 keys
-    (a large contracted mode): per-block dense sums by key, added in block
+    """More than 32768 nonzeros whose remaining modes span at most 16384 keys
+    (8192 for rows of more than 3 indices; a large contracted mode): per-block
+    dense sums by key, added in block
     order, present keys written in key order.  Against the oracle (FP32 also
     with FP32 output, rounded once), bitwise repeatable."""
     P = _api()
