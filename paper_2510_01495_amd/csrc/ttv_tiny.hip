@@ -26,17 +26,18 @@ namespace {
 
 constexpr int kTinyThreads = 1024;
 // keys held in LDS: 16384 FP64 sums (128 KB) beside the row stage of rows of
-// up to 3 indices, 8192 beside the wider ones
+// up to 3 indices, 8192 beside the wider ones; a product uses the smallest
+// capacity that holds its keys (less to clear and scan)
 template <int MO>
 constexpr int key_cap() { return MO <= 3 ? 2 * kTinyKeys : kTinyKeys; }
 
-template <typename IdxT, int F, int MO>
+template <typename IdxT, int F, int MO, int KC>
 __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range, int32_t* err) {
   using FO = FormOps<F>;
   using In = typename FO::In;
   constexpr int NW = kTinyThreads / 64;
   constexpr int IPT = MO <= 5 ? 4 : 2;  // nonzeros per lane per tile
-  constexpr int KC = key_cap<MO>();
+  static_assert(KC <= key_cap<MO>() && KC % kTinyThreads == 0, "LDS sums by key");
   constexpr int KPT = KC / kTinyThreads;  // keys per thread when writing
   __shared__ double acc[KC];
   __shared__ unsigned pres[KC / 32];
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
 // ---------------------------------------------------------------------------
 constexpr int kKeyedBlocks = 512;  // most blocks: the sum order depends on nnz only
 
-template <typename IdxT, int F, int MO>
+template <typename IdxT, int F, int MO, int KC>
 __global__ __launch_bounds__(kTinyThreads) void k_keyed(TDesc D, long long range, int32_t* err, double* partials,
                                                          unsigned* present) {
   using FO = FormOps<F>;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_keyed(TDesc D, long long range
   constexpr int NW = kTinyThreads / 64;
   constexpr int IPT = MO <= 5 ? 4 : 2;
   constexpr long long TA = (long long)kTinyThreads * IPT;
-  constexpr int KC = key_cap<MO>();
+  static_assert(KC <= key_cap<MO>() && KC % kTinyThreads == 0, "LDS sums by key");
   __shared__ double acc[KC];
   __shared__ unsigned pres[KC / 32];
   __shared__ IdxT stage[NW][64 * MO];
@@ -278,19 +279,24 @@ int launch_keyed(const PipePlan& P, void* ws, hipStream_t s) {
   auto go = [&](auto idx_tag, auto form_tag) {
     using IdxT = decltype(idx_tag);
     constexpr int F = decltype(form_tag)::value;
-    if (mo <= 3)
-      hipLaunchKernelGGL((k_keyed<IdxT, F, 3>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials, present);
-    else if (mo <= 5)
-      hipLaunchKernelGGL((k_keyed<IdxT, F, 5>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials, present);
-    else
-      hipLaunchKernelGGL((k_keyed<IdxT, F, kMaxOrder>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials,
+    const bool wide = range > kTinyKeys;  // only rows of up to 3 indices get here with more keys
+    if (mo <= 3 && wide)
+      hipLaunchKernelGGL((k_keyed<IdxT, F, 3, key_cap<3>()>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err,
+                         partials, present);
+    else if (mo <= 3)
+      hipLaunchKernelGGL((k_keyed<IdxT, F, 3, kTinyKeys>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials,
                          present);
+    else if (mo <= 5)
+      hipLaunchKernelGGL((k_keyed<IdxT, F, 5, kTinyKeys>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err, partials,
+                         present);
+    else
+      hipLaunchKernelGGL((k_keyed<IdxT, F, kMaxOrder, kTinyKeys>), dim3(G), dim3(kTinyThreads), 0, s, D, range, err,
+                         partials, present);
     hipLaunchKernelGGL(k_keyed_sum, dim3((unsigned)((range + 255) / 256)), dim3(256), 0, s, partials, G, range, y);
-    if (mo <= 3)
+    if (wide)
       hipLaunchKernelGGL((k_keyed_write<IdxT, key_cap<3>()>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y, present);
     else
-      hipLaunchKernelGGL((k_keyed_write<IdxT, key_cap<kMaxOrder>()>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y,
-                         present);
+      hipLaunchKernelGGL((k_keyed_write<IdxT, kTinyKeys>), dim3(1), dim3(kTinyThreads), 0, s, D, range, y, present);
   };
   auto by_form = [&](auto idx_tag) {
     if (P.form == kF64)
@@ -323,12 +329,15 @@ int launch_tiny(const PipePlan& P, void* ws, hipStream_t s) {
   auto go = [&](auto idx_tag, auto form_tag) {
     using IdxT = decltype(idx_tag);
     constexpr int F = decltype(form_tag)::value;
-    if (mo <= 3)
-      hipLaunchKernelGGL((k_tiny<IdxT, F, 3>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+    if (mo <= 3 && range > kTinyKeys)  // only rows of up to 3 indices get here with more keys
+      hipLaunchKernelGGL((k_tiny<IdxT, F, 3, key_cap<3>()>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+    else if (mo <= 3)
+      hipLaunchKernelGGL((k_tiny<IdxT, F, 3, kTinyKeys>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
     else if (mo <= 5)
-      hipLaunchKernelGGL((k_tiny<IdxT, F, 5>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+      hipLaunchKernelGGL((k_tiny<IdxT, F, 5, kTinyKeys>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
     else
-      hipLaunchKernelGGL((k_tiny<IdxT, F, kMaxOrder>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range, err);
+      hipLaunchKernelGGL((k_tiny<IdxT, F, kMaxOrder, kTinyKeys>), dim3(1), dim3(kTinyThreads), 0, s, P.d0, range,
+                         err);
   };
   auto by_form = [&](auto idx_tag) {
     if (P.form == kF64)
