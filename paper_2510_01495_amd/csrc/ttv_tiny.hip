@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny(TDesc D, long long range,
 }
 
 // ---------------------------------------------------------------------------
-// Larger products whose remaining modes span at most kTinyKeys keys (a large
+// Larger products whose remaining modes span at most key_cap keys (a large
 // contracted mode: many nonzeros per output row).  The same dense sums by
 // key, per block: a fixed number of blocks take tiles in a fixed order, each
 // adds its products into its own LDS sums (in order, as above) and ORs its
