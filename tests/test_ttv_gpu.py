@@ -348,12 +348,15 @@ def test_validate_reports_bad_index(nnz, shape):
     ((10, 20, 50_000, 30), 2, 300_000, np.int32, np.float32),
     ((7, 40_000, 3, 2, 5), 1, 200_000, np.int32, np.float64),
     ((120, 100_000, 130), 1, 500_000, np.int64, np.float32),
+    ((128, 50_000, 128), 1, 300_000, np.int32, np.float64),
+    ((40, 20_000, 30, 10), 1, 100_000, np.int64, np.float64),
 ])
 @pytest.mark.parametrize("soa", [False, True])
 def test_few_keys_many_nonzeros(shape, mode, nnz, idx, val, soa):
     """More than 32768 nonzeros whose remaining modes span at most 16384 keys
     (8192 for rows of more than 3 indices; a large contracted mode): per-block
-    dense sums by key, added in block
+    dense sums by key (exactly 16384 keys at order 3; 12000 keys at order 4
+    go to the sorting pipeline instead), added in block
     order, present keys written in key order.  Against the oracle (FP32 also
     with FP32 output, rounded once), bitwise repeatable."""
     P = _api()
