@@ -27,6 +27,7 @@ from .ttv_oracle import (  # noqa: F401
     remaining_modes,
     ttv,
     ttv_coords,
+    ttv_plain,
     ttv_entries,
     ttv_vjp,
 )

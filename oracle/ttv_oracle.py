@@ -116,11 +116,53 @@ def ttv(subs, vals, shape, mode, v):
     order, starts = _group_rows(cols)
     m = starts.size - 1
     newsubs = cols[order[starts[:-1]]] if m else np.zeros((0, d - 1), dtype=np.int64)
-    ps = p[order]
-    newvals = np.empty(m, dtype=np.float64)
-    for g in range(m):
-        newvals[g] = math.fsum(ps[starts[g]:starts[g + 1]].tolist())
+    newvals = _group_fsums(p[order], starts)
     return newsubs.reshape(m, d - 1), newvals, newshape
+
+
+def _group_fsums(ps: np.ndarray, starts: np.ndarray) -> np.ndarray:
+    """Correctly rounded sum of every run ps[starts[g]:starts[g+1]].
+
+    A run of one value sums to that value, and a run of two to their FP64
+    sum (one IEEE-754 addition is correctly rounded), so ``math.fsum`` is
+    only called for runs of three or more."""
+    m = starts.size - 1
+    out = np.empty(m, dtype=np.float64)
+    if m == 0:
+        return out
+    sizes = np.diff(starts)
+    first = starts[:-1]
+    one = sizes == 1
+    out[one] = ps[first[one]]
+    two = sizes == 2
+    out[two] = ps[first[two]] + ps[first[two] + 1]
+    for g in np.nonzero(sizes >= 3)[0].tolist():
+        out[g] = math.fsum(ps[starts[g]:starts[g + 1]].tolist())
+    return out
+
+
+def ttv_plain(subs, vals, shape, mode, v):
+    """Sparse TTV (Eq. 3) the plain NumPy way: products in FP64, rows grouped
+    with ``np.lexsort`` and each group summed with ``np.add.reduceat`` (left to
+    right in sorted order, so not correctly rounded).  Same coordinates as
+    ``ttv``; values within FP64 rounding of it.  This is the CPU baseline the
+    benchmark times, not the correctness reference."""
+    subs = np.asarray(subs)
+    d, nnz = _check(subs, vals, shape)
+    R = remaining_modes(d, mode)
+    v = np.asarray(v)
+    if v.shape != (int(shape[mode]),):
+        raise OracleError("vector length must equal the contracted dimension")
+    newshape = tuple(int(shape[j]) for j in R)
+    p = products(subs, vals, mode, v)
+    cols = subs[:, R].astype(np.int64)
+    order, starts = _group_rows(cols)
+    m = starts.size - 1
+    if m == 0:
+        return np.zeros((0, d - 1), dtype=np.int64), np.zeros(0), newshape
+    newsubs = cols[order[starts[:-1]]]
+    newvals = np.add.reduceat(p[order], starts[:-1])
+    return newsubs, newvals, newshape
 
 
 def ttv_coords(subs, shape, mode):
@@ -217,10 +259,8 @@ def allbut(subs, vals, shape, keep, vecs) -> np.ndarray:
     p = allbut_products(subs, vals, keep, vecs)
     out = np.zeros(int(shape[keep]), dtype=np.float64)
     order, starts = _group_rows(subs[:, [keep]].astype(np.int64))
-    ps = p[order]
-    ks = subs[order, keep]
-    for g in range(starts.size - 1):
-        out[int(ks[starts[g]])] = math.fsum(ps[starts[g]:starts[g + 1]].tolist())
+    if starts.size > 1:
+        out[subs[order[starts[:-1]], keep]] = _group_fsums(p[order], starts)
     return out
 
 
@@ -230,10 +270,8 @@ def allbut_abs(subs, vals, shape, keep, vecs) -> np.ndarray:
     p = np.abs(allbut_products(subs, vals, keep, vecs))
     out = np.zeros(int(shape[keep]), dtype=np.float64)
     order, starts = _group_rows(subs[:, [keep]].astype(np.int64))
-    ps = p[order]
-    ks = subs[order, keep]
-    for g in range(starts.size - 1):
-        out[int(ks[starts[g]])] = math.fsum(ps[starts[g]:starts[g + 1]].tolist())
+    if starts.size > 1:
+        out[subs[order[starts[:-1]], keep]] = _group_fsums(p[order], starts)
     return out
 
 
@@ -378,10 +416,8 @@ def ttv_vjp(subs, vals, shape, mode, v, grad_out):
     terms = a * ge
     grad_v = np.zeros(int(shape[mode]), dtype=np.float64)
     order, starts = _group_rows(subs[:, [mode]].astype(np.int64))
-    ts = terms[order]
-    ks = subs[order, mode]
-    for s in range(starts.size - 1):
-        grad_v[int(ks[starts[s]])] = math.fsum(ts[starts[s]:starts[s + 1]].tolist())
+    if starts.size > 1:
+        grad_v[subs[order[starts[:-1]], mode]] = _group_fsums(terms[order], starts)
     return grad_v, grad_vals
 
 
@@ -418,10 +454,8 @@ def allbut_vjp(subs, vals, shape, keep, vecs, grad_out):
         terms = a * prod_except(m)
         out = np.zeros(int(shape[m]), dtype=np.float64)
         order, starts = _group_rows(subs[:, [m]].astype(np.int64))
-        ts = terms[order]
-        ks = subs[order, m]
-        for s in range(starts.size - 1):
-            out[int(ks[starts[s]])] = math.fsum(ts[starts[s]:starts[s + 1]].tolist())
+        if starts.size > 1:
+            out[subs[order[starts[:-1]], m]] = _group_fsums(terms[order], starts)
         grad_vecs[m] = out
     return grad_vecs, grad_vals
 

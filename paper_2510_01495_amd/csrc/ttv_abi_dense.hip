@@ -205,6 +205,27 @@ int check_common(const ttv_coo_desc* X, int keep_or_mode, int& form, int& idx64)
   return plan_tensor(X, nc, modes, 0, D, form, idx64);
 }
 
+// Largest partials region of the adjoint of the all-but-one product over
+// every subset of requested vector gradients (null grad_vecs entries are
+// skipped): a pass with fewer accumulators uses less LDS, so it can run more
+// blocks per CU and write more partials than the pass of all modes.
+size_t allbut_bwd_partials(const ttv_coo_desc* X, int keep) {
+  int all[TTV_MAX_ORDER], na = 0;
+  for (int j = 0; j < X->order; ++j)
+    if (j != keep) all[na++] = j;
+  size_t part = 0;
+  for (unsigned sub = 0; sub < (1u << na); ++sub) {
+    int modes[TTV_MAX_ORDER], nm = 0;
+    for (int i = 0; i < na; ++i)
+      if (sub & (1u << i)) modes[nm++] = all[i];
+    Pass passes[TTV_MAX_ORDER];
+    int npass, fb[TTV_MAX_ORDER], nfb;
+    plan_passes(X, modes, nm, true, passes, npass, fb, nfb);
+    for (int p = 0; p < npass; ++p) part = std::max(part, pass_ws(passes[p]));
+  }
+  return part;
+}
+
 // Workspace of the all-but-one product / its adjoint.
 struct DenseWs {
   size_t total = kHdr;
@@ -212,7 +233,7 @@ struct DenseWs {
 };
 
 DenseWs layout_dense(const ttv_coo_desc* X, int flags, const Pass* passes, int npass, const int* fb, int nfb,
-                     size_t segmap_ws, bool need_seg) {
+                     size_t segmap_ws, bool need_seg, size_t min_part = 0) {
   DenseWs W;
   size_t pipe = segmap_ws;
   for (int i = 0; i < nfb; ++i) pipe = std::max(pipe, fallback_pipe_ws(X, fb[i], flags));
@@ -226,7 +247,7 @@ DenseWs layout_dense(const ttv_coo_desc* X, int flags, const Pass* passes, int n
     W.tmp_off = o;
     o = align256(o + tmp_bytes(X));
   }
-  size_t part = 0;
+  size_t part = min_part;
   for (int p = 0; p < npass; ++p) part = std::max(part, pass_ws(passes[p]));
   W.part_off = o;
   o = align256(o + part);
@@ -311,7 +332,7 @@ int ttv_coo_backward_workspace(const ttv_coo_desc* X, int32_t kind, int32_t mode
     for (int j = 0; j < X->order; ++j)
       if (j != mode_or_keep) modes[nm++] = j;
     plan_passes(X, modes, nm, true, passes, npass, fb, nfb);
-    *bytes = layout_dense(X, flags, passes, npass, fb, nfb, 0, false).total;
+    *bytes = layout_dense(X, flags, passes, npass, fb, nfb, 0, false, allbut_bwd_partials(X, mode_or_keep)).total;
     return TTV_OK;
   }
   if (kind != TTV_BWD_SPARSE) return TTV_E_ARG;
@@ -353,9 +374,11 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, 
     for (int j = 0; j < X->order; ++j)
       if (j != keep) all[na++] = j;
     plan_passes(X, all, na, true, wpasses, wnp, wfb, wnfb);  // what the workspace query sized
-    const DenseWs W = layout_dense(X, flags, wpasses, wnp, wfb, wnfb, 0, false);
+    const DenseWs W = layout_dense(X, flags, wpasses, wnp, wfb, wnfb, 0, false, allbut_bwd_partials(X, keep));
     if (!ws || ws_bytes < W.total) return TTV_E_WORKSPACE;
     plan_passes(X, modes, nm, grad_vals != nullptr, passes, npass, fb, nfb);
+    for (int p = 0; p < npass; ++p)  // every pass's partials fit the region sized above
+      if (W.part_off + pass_ws(passes[p]) > W.total) return TTV_E_WORKSPACE;
     const void* fac[TTV_MAX_ORDER] = {nullptr};
     for (int j = 0; j < X->order; ++j) fac[j] = (j == keep) ? grad_out : vecs[j];
     for (int i = 0; i < nfb; ++i) {
@@ -385,6 +408,11 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, 
     plan_passes(X, &mode, 1, true, wpasses, wnp, wfb, wnfb);
     const DenseWs W = layout_dense(X, flags, wpasses, wnp, wfb, wnfb, P.L.end, true);
     if (!ws || ws_bytes < W.total) return TTV_E_WORKSPACE;
+    int modes[1] = {mode};
+    const int nm = grad_vecs[mode] ? 1 : 0;
+    plan_passes(X, modes, nm, grad_vals != nullptr, passes, npass, fb, nfb);
+    for (int p = 0; p < npass; ++p)
+      if (W.part_off + pass_ws(passes[p]) > W.total) return TTV_E_WORKSPACE;
     // 1. the output row of every nonzero (the forward's grouping)
     int32_t* seg = reinterpret_cast<int32_t*>(w + W.seg_off);
     P.d0.seg_out = seg;
@@ -393,9 +421,6 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, 
     rc = launch_pipeline(P, w + W.pipe_off, s);
     if (rc) return rc;
     // 2. grad_v keyed by the contracted mode, grad_vals per nonzero
-    int modes[1] = {mode};
-    const int nm = grad_vecs[mode] ? 1 : 0;
-    plan_passes(X, modes, nm, grad_vals != nullptr, passes, npass, fb, nfb);
     const void* fac[TTV_MAX_ORDER] = {nullptr};
     fac[mode] = vecs[mode];
     for (int i = 0; i < nfb; ++i) {

@@ -587,3 +587,146 @@ def test_mttkrp_integer_exact():
             want[subs[e, mode], r] += t
     got = oracle.mttkrp(subs, vals.astype(np.float64), shape, mode, U)
     assert np.array_equal(got, want.astype(np.float64))
+
+
+# --------------------------------------------------------------------------
+# The condition scales (sums of |products|) that the GPU tolerances multiply.
+# --------------------------------------------------------------------------
+# Mixed-sign version of the hand tensor: a = (1, -2, 3, -4, 5), x = (10, -100).
+#   mode 2: (0,0): |1*10| + |5*-100| = 510, (0,1): |-2*10| = 20,
+#           (1,0): |3*-100| = 300,          (1,1): |-4*-100| = 400
+HAND_SIGNED_VALS = np.array([1.0, -2.0, 3.0, -4.0, 5.0])
+HAND_SIGNED_X = np.array([10.0, -100.0])
+
+
+def test_abs_sums_hand_value():
+    coords = np.array([[0, 0], [0, 1], [1, 0], [1, 1]])
+    s = oracle.abs_sums(HAND_SUBS, HAND_SIGNED_VALS, (2, 2, 2), 2, HAND_SIGNED_X, coords)
+    assert s.tolist() == [510.0, 20.0, 300.0, 400.0]
+    # the signed sums themselves: 10 - 500, -20, -300, 400
+    ns, nv, _ = oracle.ttv(HAND_SUBS, HAND_SIGNED_VALS, (2, 2, 2), 2, HAND_SIGNED_X)
+    assert nv.tolist() == [-490.0, -20.0, -300.0, 400.0]
+
+
+def test_allbut_abs_hand_value():
+    # keep 0, x1 = (1, -3), x2 = (-2, 5): |a_ijk x1_j x2_k| per i
+    #   i=0: |1*1*-2| + |-2*-3*-2| + |5*1*5| = 2 + 12 + 25 = 39
+    #   i=1: |3*1*5| + |-4*-3*5| = 15 + 60 = 75
+    vecs = [None, np.array([1.0, -3.0]), np.array([-2.0, 5.0])]
+    s = oracle.allbut_abs(HAND_SUBS, HAND_SIGNED_VALS, (2, 2, 2), 0, vecs)
+    assert s.tolist() == [39.0, 75.0]
+    y = oracle.allbut(HAND_SUBS, HAND_SIGNED_VALS, (2, 2, 2), 0, vecs)
+    assert y.tolist() == [-2.0 - 12.0 + 25.0, 15.0 + 60.0]
+
+
+def test_mttkrp_abs_hand_value():
+    # HAND tensor with signed values, mode 0, U1 = [[1, -2], [3, 4]], U2 = [[-5, 6], [7, -8]]
+    #   row 0, r=0: |1*1*-5| + |-2*3*-5| + |5*1*7| = 5 + 30 + 35 = 70
+    #   row 0, r=1: |1*-2*6| + |-2*4*6| + |5*-2*-8| = 12 + 48 + 80 = 140
+    #   row 1, r=0: |3*1*7| + |-4*3*7| = 21 + 84 = 105
+    #   row 1, r=1: |3*-2*-8| + |-4*4*-8| = 48 + 128 = 176
+    U = [None, np.array([[1.0, -2.0], [3.0, 4.0]]), np.array([[-5.0, 6.0], [7.0, -8.0]])]
+    s = oracle.mttkrp_abs(HAND_SUBS, HAND_SIGNED_VALS, (2, 2, 2), 0, U)
+    assert s.tolist() == [[70.0, 140.0], [105.0, 176.0]]
+
+
+@pytest.mark.parametrize("d,seed", [(2, 0), (3, 1), (4, 2), (5, 3)])
+def test_abs_sums_are_the_product_of_absolute_values(d, seed):
+    """abs_sums (grouped through a linear cell number and a dict) equals the
+    lexsort-grouped product of |vals| with |v|; it bounds every |sum| and
+    equals it on same-sign data."""
+    rng = np.random.default_rng(700 + seed)
+    dims = tuple(int(s) for s in rng.integers(2, 7, d))
+    nnz = 300
+    subs = np.column_stack([rng.integers(0, s, nnz) for s in dims])
+    vals = rng.standard_normal(nnz)
+    for mode in range(d):
+        v = rng.standard_normal(dims[mode])
+        ns, nv, _ = oracle.ttv(subs, vals, dims, mode, v)
+        s = oracle.abs_sums(subs, vals, dims, mode, v, ns)
+        _, want, _ = oracle.ttv(subs, np.abs(vals), dims, mode, np.abs(v))
+        assert np.array_equal(s, want)
+        assert np.all(np.abs(nv) <= s * (1 + 1e-15))
+        _, pos, _ = oracle.ttv(subs, np.abs(vals), dims, mode, np.abs(v))
+        assert np.array_equal(oracle.abs_sums(subs, np.abs(vals), dims, mode, np.abs(v), ns), pos)
+
+
+@pytest.mark.parametrize("d,seed", [(2, 0), (3, 1), (4, 2)])
+def test_allbut_abs_is_allbut_of_absolute_values(d, seed):
+    rng = np.random.default_rng(800 + seed)
+    dims = tuple(int(s) for s in rng.integers(2, 9, d))
+    subs = np.column_stack([rng.integers(0, s, 400) for s in dims])
+    vals = rng.standard_normal(400)
+    vecs = [rng.standard_normal(n) for n in dims]
+    D = np.abs(dense_of(synth.COO(subs, vals, dims)))  # (duplicates may cancel: only a lower bound)
+    for keep in range(d):
+        s = oracle.allbut_abs(subs, vals, dims, keep, vecs)
+        want = oracle.allbut(subs, np.abs(vals), dims, keep, [np.abs(w) for w in vecs])
+        assert np.array_equal(s, want)
+        # dense brute force of |X| contracted with |v|: a lower bound of s
+        letters = "abcdefgh"[:d]
+        terms = [letters] + [letters[j] for j in range(d) if j != keep]
+        lb = np.einsum(",".join(terms) + "->" + letters[keep], D,
+                       *[np.abs(vecs[j]) for j in range(d) if j != keep])
+        assert np.all(lb <= s * (1 + 1e-13) + 1e-300)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_mttkrp_abs_brute_force(mode):
+    """mttkrp_abs equals the dense contraction of |X| with |U| when no
+    coordinate repeats (so |sum of duplicates| = sum of |duplicates|)."""
+    rng = np.random.default_rng(90 + mode)
+    shape = (5, 6, 4)
+    ids = rng.choice(5 * 6 * 4, size=70, replace=False)
+    subs = np.stack(np.unravel_index(ids, shape), axis=1)
+    vals = rng.standard_normal(70)
+    U = [None if j == mode else rng.standard_normal((s, 3)) for j, s in enumerate(shape)]
+    D = np.abs(dense_of(synth.COO(subs, vals, shape)))
+    letters = "abc"
+    terms = [letters] + [letters[j] + "r" for j in range(3) if j != mode]
+    want = np.einsum(",".join(terms) + "->" + letters[mode] + "r", D, *[np.abs(U[j]) for j in range(3) if j != mode])
+    got = oracle.mttkrp_abs(subs, vals, shape, mode, U)
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+
+
+def test_group_sums_match_exact_rational_sums():
+    """Runs of one, two and more products: each output equals the exact
+    rational sum of its products rounded once (Fraction -> float is correctly
+    rounded)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(31)
+    sizes = [1, 2, 3, 1, 2, 5, 2, 1, 9, 2, 2, 4]
+    rows = np.repeat(np.arange(len(sizes)), sizes)
+    n = rows.size
+    subs = np.stack([rows, np.arange(n) % 3, rng.integers(0, 4, n)], axis=1)
+    vals = rng.standard_normal(n) * 10.0 ** rng.integers(-8, 9, n)
+    v = rng.standard_normal(3)
+    ns, nv, _ = oracle.ttv(subs, vals, (len(sizes), 3, 4), 1, v)
+    p = oracle.products(subs, vals, 1, v)
+    for g in range(len(sizes)):
+        sel = np.nonzero(rows == g)[0]
+        # rows of group g with the same mode-2 index form one output entry
+        for k in np.unique(subs[sel, 2]):
+            ii = sel[subs[sel, 2] == k]
+            exact = float(sum(Fraction(float(p[e])) for e in ii))
+            r = np.nonzero((ns[:, 0] == g) & (ns[:, 1] == k))[0]
+            assert r.size == 1 and nv[r[0]] == exact
+
+
+@pytest.mark.parametrize("d,seed", [(2, 0), (3, 1), (4, 2)])
+def test_plain_mode_matches(d, seed):
+    """The plain lexsort + reduceat product (the CPU baseline) has the
+    coordinates of np.unique and the dense brute-force values."""
+    rng = np.random.default_rng(900 + seed)
+    dims = tuple(int(s) for s in rng.integers(2, 8, d))
+    subs = np.column_stack([rng.integers(0, s, 500) for s in dims])
+    vals = rng.random(500)
+    D = dense_of(synth.COO(subs, vals, dims))
+    for mode in range(d):
+        v = rng.random(dims[mode])
+        ns, nv, shp = oracle.ttv_plain(subs, vals, dims, mode, v)
+        R = [j for j in range(d) if j != mode]
+        assert np.array_equal(ns, np.unique(subs[:, R], axis=0))
+        Y = np.tensordot(D, v, axes=([mode], [0]))
+        assert np.allclose(nv, Y[tuple(ns.T)], rtol=1e-13, atol=0)
+        assert shp == tuple(dims[j] for j in R)
