@@ -30,7 +30,18 @@
  *     anything is enqueued.  Device-side failures are reported by
  *     ttv_check_device_error after the work has run.
  *   - Results are deterministic: the same inputs give bitwise-identical
- *     outputs on every run (no floating-point atomics anywhere).
+ *     outputs on every run.  No floating-point atomic touches global
+ *     memory.  Several kernels add FP64 values into LDS with ds_add_f64
+ *     (dense all-but-one and adjoint accumulators, the one-block and
+ *     dense-key small paths, leaves whose keys fit 16 bits); their order is
+ *     fixed by having a block's waves take turns and by gfx950's LDS serving
+ *     the lanes of one instruction that hit the same address in ascending
+ *     lane order.  That lane order is measured behaviour of the hardware, not
+ *     a documented guarantee; if it failed, those sums would still be
+ *     correct but could differ in the last bits between runs.  The sort's
+ *     stable ranks use the same property: every sorted leaf checks on the
+ *     device that its keys ascend and reports TTV_E_DEVICE otherwise, so a
+ *     violation cannot produce unsorted output silently.
  *   - No C++ exception crosses this interface.
  */
 #ifndef TTV_H
@@ -64,7 +75,8 @@ enum {
   TTV_E_INDEX = -8,     /* (device) an index was out of range (TTV_VALIDATE) */
   TTV_E_HIP = -9,       /* a HIP runtime call failed: see ttv_last_hip_error */
   TTV_E_SIZE = -10,     /* nnz or a dimension exceeds what this build supports */
-  TTV_E_DEVICE = -11,   /* (device) an internal bounded wait gave up */
+  TTV_E_DEVICE = -11,   /* (device) an internal bounded wait gave up, a capacity
+                           check failed, or a sorted leaf's keys did not ascend */
   TTV_E_ARG = -12       /* any other invalid argument */
 };
 
@@ -88,10 +100,16 @@ enum {
  *   TTV_F64: FP64 vals and vectors; each product is rounded once and the
  *            sums are FP64.  Results are FP64.
  *   TTV_F32: FP32 vals and vectors; every product is kept exactly as an FP32
- *            pair (TwoProduct via fmaf) and the sums are compensated FP32
- *            (Dot2: TwoSum plus an FP32 error accumulator); partial sums of
- *            one output that are combined across blocks are combined in
- *            FP64.  Results are FP32 (FP64 with TTV_OUT_F64).
+ *            pair (TwoProduct via fmaf).  Sums that run through the sort
+ *            (segmented scans over sorted leaves, partial sums of large
+ *            single-key buckets, MTTKRP and full-contraction lanes) are
+ *            compensated FP32 (Dot2: TwoSum plus an FP32 error term), with
+ *            partial sums of one output that cross blocks combined in FP64.
+ *            Sums formed by LDS accumulation (the all-but-one product and
+ *            the adjoints, the one-block and dense-key small paths, leaves
+ *            whose keys fit 16 bits) add the exact product pair widened to
+ *            FP64 instead: at least as accurate.  Either way the value is
+ *            rounded once to FP32 on output (FP64 with TTV_OUT_F64).
  */
 typedef struct {
   int32_t order;        /* d, 2..TTV_MAX_ORDER */
@@ -207,8 +225,9 @@ int ttv_coo_full(const ttv_coo_desc* X, const void* const* vecs, const int64_t* 
  *   y[i] = sum over nonzeros e with subs(e, keep) = i of
  *          vals[e] * prod_{j != keep} vecs[j][subs(e, j)]
  * (factors multiplied in ascending mode order).  Entries no nonzero reaches
- * are 0.  Accumulation is atomics-free: every block reduces its tiles into a
- * private dense partial, and the partials are summed in a fixed order.
+ * are 0.  No global atomics: every block adds its tiles' products into a
+ * private dense FP64 partial in LDS (ds_add_f64 in a fixed order, see the
+ * conventions above), and the partials are summed in a fixed block order.
  *   vecs     host array of d device pointers (vecs[keep] is ignored)
  *   vec_lens host array of d lengths (vec_lens[keep] is ignored)
  *   y        device, shape[keep] values (FP64, or FP32 unless TTV_OUT_F64)

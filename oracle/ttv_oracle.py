@@ -120,6 +120,26 @@ def ttv(subs, vals, shape, mode, v):
     return newsubs.reshape(m, d - 1), newvals, newshape
 
 
+def ttv_scaled(subs, vals, shape, mode, v):
+    """``ttv`` together with each output's condition scale: returns
+    (newsubs, newvals, newshape, abssums), abssums[r] = fsum of |products| of
+    output r (one grouping serves both)."""
+    subs = np.asarray(subs)
+    d, nnz = _check(subs, vals, shape)
+    R = remaining_modes(d, mode)
+    v = np.asarray(v)
+    if v.shape != (int(shape[mode]),):
+        raise OracleError("vector length must equal the contracted dimension")
+    newshape = tuple(int(shape[j]) for j in R)
+    p = products(subs, vals, mode, v)
+    cols = subs[:, R].astype(np.int64)
+    order, starts = _group_rows(cols)
+    m = starts.size - 1
+    newsubs = cols[order[starts[:-1]]] if m else np.zeros((0, d - 1), dtype=np.int64)
+    ps = p[order]
+    return newsubs.reshape(m, d - 1), _group_fsums(ps, starts), newshape, _group_fsums(np.abs(ps), starts)
+
+
 def _group_fsums(ps: np.ndarray, starts: np.ndarray) -> np.ndarray:
     """Correctly rounded sum of every run ps[starts[g]:starts[g+1]].
 

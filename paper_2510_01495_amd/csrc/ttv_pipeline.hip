@@ -1439,10 +1439,19 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       if (j < nj && p < n) {
         if (p == 0) {
           hd = true;
-        } else if (wide) {
-          hd = R[si[p]].key != R[si[p - 1]].key;
         } else {
-          hd = sk[p] != sk[p - 1];
+          // the sort's ranks rely on LDS serving same-address lanes in lane
+          // order; keys that do not ascend are reported, never written
+          bool desc;
+          if (wide) {
+            const uint64_t a = R[si[p - 1]].key, b = R[si[p]].key;
+            hd = b != a;
+            desc = b < a;
+          } else {
+            hd = sk[p] != sk[p - 1];
+            desc = sk[p] < sk[p - 1];
+          }
+          if (desc) set_error(C, TTV_E_DEVICE);
         }
       }
       hm[j] = ballot(hd);

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import say, to_gpu
+from gpu_util import check_values, say, to_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -30,11 +30,10 @@ def _run(X, vecs_np, *, soa=False, out_f64=False, flags=0):
     return op
 
 
-def _check(X, vecs_np, y, tol, what):
+def _check(X, vecs_np, y, tol, what, componentwise=None):
     want = oracle.full(X.subs, X.vals, X.shape, vecs_np)
     scale = oracle.full_abs(X.subs, X.vals, X.shape, vecs_np)
-    got = float(y)
-    assert abs(got - want) <= tol * scale + 1e-300, f"{what}: {got!r} vs {want!r} (scale {scale:.3e})"
+    check_values([float(y)], [want], [scale], tol, what, componentwise)
 
 
 def _tensor(rng, d, nnz, idx=np.int64, val=np.float64, dist="normal"):
@@ -82,7 +81,7 @@ def test_fp32_output_and_compensation():
     op64 = _run(X, vecs, out_f64=True)
     op32 = _run(X, vecs)
     assert op32.y.dtype.itemsize == 4
-    _check(X, vecs, op64.y.item(), C32_TOL, "c32")
+    _check(X, vecs, op64.y.item(), C32_TOL, "c32", componentwise=False)  # cancellation by design
     assert np.float32(op64.y.item()) == op32.y.item()
 
 

@@ -730,3 +730,19 @@ def test_plain_mode_matches(d, seed):
         Y = np.tensordot(D, v, axes=([mode], [0]))
         assert np.allclose(nv, Y[tuple(ns.T)], rtol=1e-13, atol=0)
         assert shp == tuple(dims[j] for j in R)
+
+
+@pytest.mark.parametrize("d,seed", [(2, 4), (3, 5), (5, 6)])
+def test_scaled_product_matches_its_parts(d, seed):
+    """ttv_scaled's values are ttv's and its scales are ttv of |vals|, |v|."""
+    rng = np.random.default_rng(1000 + seed)
+    dims = tuple(int(s) for s in rng.integers(2, 8, d))
+    subs = np.column_stack([rng.integers(0, s, 600) for s in dims])
+    vals = rng.standard_normal(600)
+    for mode in range(d):
+        v = rng.standard_normal(dims[mode])
+        ns, nv, shp, sc = oracle.ttv_scaled(subs, vals, dims, mode, v)
+        ws, wv, wshp = oracle.ttv(subs, vals, dims, mode, v)
+        _, wsc, _ = oracle.ttv(subs, np.abs(vals), dims, mode, np.abs(v))
+        assert np.array_equal(ns, ws) and np.array_equal(nv, wv) and shp == wshp
+        assert np.array_equal(sc, wsc)
