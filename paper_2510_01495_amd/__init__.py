@@ -9,6 +9,7 @@ only supplies device memory and streams.
 from . import _lib  # noqa: F401
 from .api import (  # noqa: F401
     AllButOp,
+    BackwardOp,
     BatchedTTV,
     FullOp,
     MTTKRP,
@@ -27,5 +28,5 @@ from .api import (  # noqa: F401
     ttv_pyttb,
 )
 
-__all__ = ["AllButOp", "BatchedTTV", "FullOp", "MTTKRP", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
+__all__ = ["AllButOp", "BackwardOp", "BatchedTTV", "FullOp", "MTTKRP", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
            "mttkrp", "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]

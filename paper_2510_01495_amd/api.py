@@ -308,6 +308,53 @@ def ttv_backward(subs, vals, shape, kind: str, mode: int, vecs, grad_out, *, wan
     return gv, (gvals[:vals.numel()] if gvals is not None else None)
 
 
+class BackwardOp:
+    """A planned adjoint (as ``ttv_backward``) with preallocated gradients and
+    workspace; ``launch(grad_out)`` enqueues it without synchronising."""
+
+    def __init__(self, subs, vals, shape, kind: str, mode: int, vecs, *, want_vecs=None, want_vals: bool = True,
+                 flags: int = 0):
+        if kind not in ("sparse", "allbut"):
+            raise ValueError("kind must be 'sparse' or 'allbut'")
+        self.lib = L.load()
+        self.subs, self.vals, self.shape, self.mode = subs, vals, tuple(int(s) for s in shape), int(mode)
+        d = len(self.shape)
+        self.kind = L.BWD_SPARSE if kind == "sparse" else L.BWD_ALLBUT
+        self.desc = coo_desc(subs, vals, self.shape)
+        if kind == "sparse":
+            want = [mode] if want_vecs is None else list(want_vecs)
+            vv = [None] * d
+            vv[mode] = vecs[mode] if isinstance(vecs, (list, tuple)) else vecs
+            self.vecs = vv
+            self.c_vecs, self.c_lens = _vec_arrays(vv, d)
+        else:
+            want = [j for j in range(d) if j != mode] if want_vecs is None else list(want_vecs)
+            self.vecs = list(vecs)
+            self.c_vecs, self.c_lens = _vec_arrays(vecs, d, skip=mode)
+        dev = subs.device
+        self.grad_vecs = [torch.empty(self.shape[j], dtype=vals.dtype, device=dev) if j in want else None
+                          for j in range(d)]
+        self.gptrs = (c_void_p * d)(*[None if g is None else g.data_ptr() for g in self.grad_vecs])
+        self.grad_vals = torch.empty(max(1, vals.numel()), dtype=vals.dtype, device=dev) if want_vals else None
+        self.flags = flags
+        nb = c_size_t(0)
+        L.check(self.lib.ttv_coo_backward_workspace(byref(self.desc), self.kind, self.mode, flags, byref(nb)),
+                "ttv_coo_backward_workspace")
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=dev)
+
+    def launch(self, grad_out):
+        if grad_out.dtype != self.vals.dtype or not grad_out.is_contiguous():
+            raise TypeError("grad_out must be contiguous with the dtype of vals")
+        rc = self.lib.ttv_coo_backward(byref(self.desc), self.kind, self.mode, self.c_vecs, self.c_lens,
+                                       grad_out.data_ptr() if grad_out.numel() else None, self.gptrs,
+                                       self.grad_vals.data_ptr() if self.grad_vals is not None else None,
+                                       self.ws.data_ptr(), self.ws.numel(), self.flags, _stream(self.subs.device))
+        L.check(rc, "ttv_coo_backward")
+
+    def device_error(self) -> int:
+        return self.lib.ttv_check_device_error(self.ws.data_ptr(), _stream(self.subs.device))
+
+
 class TTVAllButFunction(torch.autograd.Function):
     """y = X x_{j != keep} v_j as an autograd function of the vectors and of
     vals; the backward runs the library's fused adjoint kernel."""
