@@ -238,6 +238,24 @@ int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
                    void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * ttv_coo_allbut without a workspace, for callers that cannot allocate device
+ * memory (code under hipGraph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and result as ttv_coo_allbut
+ * (bitwise), except that the scratch (an error word and the blocks' FP64
+ * partial sums) lives in a static device array of TTV_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every GPU it runs on until the process ends.
+ * No allocation, no host synchronisation.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams or threads) race.
+ * Returns TTV_E_SIZE when the kept mode is too long for the LDS accumulator
+ * (more than about 18000 entries for FP64 int64 row-major input) or the
+ * partials would exceed the array, and TTV_E_ARG for TTV_VALIDATE or
+ * TTV_DROP_ZEROS.
+ * ---------------------------------------------------------------------- */
+#define TTV_NOALLOC_SCRATCH_BYTES (48u << 20)
+int ttv_coo_allbut_noalloc(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
+                           const int64_t* vec_lens, void* y, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Adjoints (reverse mode).  Eq. 3 is linear in the vector and in vals, so
  *   TTV_BWD_SPARSE  (the product of ttv_coo in mode `mode_or_keep`):
  *     grad_out  device, one value per output row of ttv_coo, in its order

@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     plan_query,
     ttv,
     ttv_allbut,
+    ttv_allbut_noalloc,
     ttv_backward,
     ttv_full,
     ttv_multi,
@@ -29,4 +30,4 @@ from .api import (  # noqa: F401
 )
 
 __all__ = ["AllButOp", "BackwardOp", "BatchedTTV", "FullOp", "MTTKRP", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
-           "mttkrp", "plan_query", "ttv", "ttv_allbut", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]
+           "mttkrp", "plan_query", "ttv", "ttv_allbut", "ttv_allbut_noalloc", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]

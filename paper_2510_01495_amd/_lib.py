@@ -58,6 +58,8 @@ SIGNATURES = {
     "ttv_coo_allbut_workspace": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_size_t)]),
     "ttv_coo_allbut": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_void_p), POINTER(c_int64), c_void_p,
                                  c_void_p, c_size_t, c_int32, c_void_p]),
+    "ttv_coo_allbut_noalloc": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_void_p), POINTER(c_int64), c_void_p,
+                                         c_int32, c_void_p]),
     "ttv_coo_backward_workspace": (c_int32, [POINTER(CooDesc), c_int32, c_int32, c_int32, POINTER(c_size_t)]),
     "ttv_coo_backward": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_void_p), POINTER(c_int64),
                                    c_void_p, POINTER(c_void_p), c_void_p, c_void_p, c_size_t, c_int32,

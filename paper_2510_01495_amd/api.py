@@ -222,6 +222,22 @@ def ttv_allbut(subs, vals, shape, keep: int, vecs, *, flags: int = 0, out_f64: b
     return op.y
 
 
+def ttv_allbut_noalloc(subs, vals, shape, keep: int, vecs, y, *, flags: int = 0):
+    """``ttv_allbut`` into a caller-provided ``y`` (shape[keep] values: FP64,
+    or FP32 for FP32 inputs unless TTV_OUT_F64) through the entry point that
+    allocates nothing (its scratch is the library's static device array).
+    Returns y."""
+    lib = L.load()
+    desc = coo_desc(subs, vals, shape)
+    c_vecs, c_lens = _vec_arrays(vecs, len(shape), skip=keep)
+    _check_tensor(y, "y")
+    if y.numel() != int(shape[keep]) or not y.is_contiguous():
+        raise ValueError("y must be a contiguous tensor of shape[keep] values")
+    L.check(lib.ttv_coo_allbut_noalloc(byref(desc), keep, c_vecs, c_lens, y.data_ptr(), flags, _stream(y.device)),
+            "ttv_coo_allbut_noalloc")
+    return y
+
+
 class FullOp:
     """Planned product with a vector in every mode (n_v = d, Sec. 3.3): the
     scalar sum over the nonzeros of vals times every mode's vector entry,

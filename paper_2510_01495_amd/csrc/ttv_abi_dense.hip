@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 
 #include "ttv.h"
 #include "ttv_dense.h"
@@ -255,6 +256,40 @@ DenseWs layout_dense(const ttv_coo_desc* X, int flags, const Pass* passes, int n
   return W;
 }
 
+// Scratch of ttv_coo_allbut_noalloc: one copy per GPU, held until the process
+// ends.  Host code never passes `scratch` itself (on the host it names a
+// stand-in, not device memory): it passes the address hipGetSymbolAddress
+// returned for the current device.
+constexpr size_t kNoAllocScratch = (size_t)48 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  if (dev < 0 || dev >= 64) return TTV_E_ARG;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_last_hip_error((int)e);
+      return TTV_E_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TTV_OK;
+}
+
 }  // namespace
 
 }  // namespace ttv
@@ -309,6 +344,46 @@ int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
     void* outs[kDenseMaxAcc] = {y, nullptr, nullptr, nullptr};
     rc = run_pass(passes[0], A, w, W.part_off, outs, nullptr, idx64, form, out_f64, s);
   }
+  if (rc) return rc;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  return TTV_OK;
+}
+
+int ttv_coo_allbut_noalloc(const ttv_coo_desc* X, int32_t keep, const void* const* vecs, const int64_t* vec_lens,
+                           void* y, int32_t flags, ttv_stream_t stream) {
+  if (flags & (TTV_DROP_ZEROS | TTV_VALIDATE)) return TTV_E_ARG;  // no workspace to read a device error from
+  int form, idx64;
+  int rc = check_common(X, keep, form, idx64);
+  if (rc) return rc;
+  if (!vecs || !vec_lens || !y) return TTV_E_NULL;
+  for (int j = 0; j < X->order; ++j) {
+    if (j == keep) continue;
+    if (vec_lens[j] != X->shape[j]) return TTV_E_SHAPE;
+    if (!vecs[j] && X->nnz > 0) return TTV_E_NULL;
+  }
+  Pass passes[TTV_MAX_ORDER];
+  int npass, fb[TTV_MAX_ORDER], nfb;
+  plan_passes(X, &keep, 1, false, passes, npass, fb, nfb);
+  if (nfb) return TTV_E_SIZE;  // the kept mode's accumulator does not fit in LDS: needs the sorting pipeline
+  const DenseWs W = layout_dense(X, flags, passes, npass, fb, nfb, 0, false);
+  if (W.total > kNoAllocScratch) return TTV_E_SIZE;
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
+  const int out_f64 = (form == kF64 || (flags & TTV_OUT_F64)) ? 1 : 0;
+  launch_zero(w, kHdr, s);
+  DenseArgs A;
+  dense_base(X, flags, A);
+  for (int j = 0; j < X->order; ++j) A.fac[j] = (j == keep) ? nullptr : vecs[j];
+  void* outs[kDenseMaxAcc] = {y, nullptr, nullptr, nullptr};
+  rc = run_pass(passes[0], A, w, W.part_off, outs, nullptr, idx64, form, out_f64, s);
   if (rc) return rc;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
