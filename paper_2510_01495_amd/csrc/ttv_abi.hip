@@ -161,10 +161,11 @@ int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
 // (it would then have to take all the remaining bits): most buckets split at
 // the second level, which takes only the few bits they need, and the level
 // after it the rest.
-static int levels_of(const TDesc& D) {
+static int levels_of(const TDesc& D, int dense_bits) {
   const int rest = std::max(0, D.keybits - D.r1);
-  int levels = 1 + (rest + kRMax - 1) / kRMax;
-  if (rest > 0 && D.nnz > 0) {
+  // buckets left with at most dense_bits key bits need no further level
+  int levels = 1 + (std::max(0, rest - dense_bits) + kRMax - 1) / kRMax;
+  if (dense_bits == 0 && rest > 0 && D.nnz > 0) {
     unsigned __int128 range = 1;
     for (int i = 0; i < D.nrem; ++i) range *= (unsigned __int128)D.dims[D.rem[i]];
     const double used = (double)((range + (((unsigned __int128)1 << rest) - 1)) >> rest);
@@ -174,14 +175,18 @@ static int levels_of(const TDesc& D) {
   return std::min(kMaxLevels, levels);
 }
 
-Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1) {
+Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1, bool dense) {
   Layout L{};
   L.count = count;
   L.levels = levels;
   L.jcap = std::max<long long>(count, total / kCap + 2);
   L.tcap = std::max<long long>(tiles1, total / T2 + L.jcap + 1);
   L.lcap = (long long)levels * (3 * ((total + kSmall - 1) / kSmall) + L.jcap) + count + 64;
-  L.pcap = total / kPureTile + total / kCap + count + 2;
+  // a dense leaf of s > kCap records holds ceil(s / kDenseTile) <= s / kDenseTile + 1 partial tiles, each
+  // a slot of at most dense_slot_words(kDenseBits) words
+  const long long dtiles = dense ? total / kDenseTile + total / kCap + count + 1 : 0;
+  L.pcap = total / kPureTile + total / kCap + dtiles + count + 2;
+  L.dpcap = dtiles * dense_slot_words(kDenseBits);
   L.words = (total + 31) / 32 + 1;
   L.wblocks = (L.words + kBitmapWordsPerBlock - 1) / kBitmapWordsPerBlock;
   size_t o = 0;
@@ -204,6 +209,7 @@ Layout make_layout(long long total, int count, int levels, int T1, int T2, long 
   L.blockpre = take((size_t)L.wblocks * sizeof(unsigned));
   L.partials = take((size_t)L.pcap * sizeof(double));
   L.ptile_leaf = take((size_t)L.pcap * sizeof(int));
+  L.dpool = take((size_t)L.dpcap * sizeof(unsigned long long));
   L.recA = take((size_t)total * sizeof(Rec));
   L.recB = take(levels > 1 ? (size_t)total * sizeof(Rec) : 0);
   L.end = o;
@@ -220,11 +226,11 @@ int finish_plan(PipePlan& P) {
   P.count = 1;
   P.total = P.d0.nnz;
   P.d0.base = 0;
-  P.levels = levels_of(P.d0);
+  P.levels = levels_of(P.d0, dense_bits_of(P.pipe_mode));
   P.T1 = choose_T1(P.total);
   P.T2 = 16384;
   P.tiles1 = (P.total + P.T1 - 1) / P.T1;
-  P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1);
+  P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1, dense_bits_of(P.pipe_mode) > 0);
   return TTV_OK;
 }
 

@@ -63,12 +63,12 @@ void apply_tuning(ttv_batch_plan* p, const Tuning& t) {
     if (p->base_r1[i] == 0) r1 = 0;  // tiny tensors stay a single bucket
     D.r1 = r1;
     const int rest = std::max(0, D.keybits - r1);
-    levels = std::max(levels, std::min(kMaxLevels, 1 + (rest + kRMax - 1) / kRMax));
+    levels = std::max(levels, std::min(kMaxLevels, 1 + (std::max(0, rest - kDenseBits) + kRMax - 1) / kRMax));
     tiles1 += (D.nnz + P.T1 - 1) / P.T1;
   }
   P.levels = levels;
   P.tiles1 = tiles1;
-  P.L = make_layout(P.total, P.count, P.levels, P.T1, P.T2, tiles1);
+  P.L = make_layout(P.total, P.count, P.levels, P.T1, P.T2, tiles1, true);
   p->tuning = t;
   if (p->descs_dev)  // the device copy follows the tuning (never while a call may run)
     hipMemcpy(p->descs_dev, P.descs.data(), sizeof(TDesc) * (size_t)P.count, hipMemcpyHostToDevice);

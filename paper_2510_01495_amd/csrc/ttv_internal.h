@@ -32,6 +32,10 @@ constexpr int kScatterIPT = 8;           // records per thread per round
 constexpr int kFinishThreads = 512;     // 8 waves
 constexpr int kFinishIPT = kCap / kFinishThreads;
 constexpr int kSortDigit = 8;            // LDS radix digit width
+constexpr int kDenseBits = 12;           // a bucket whose keys span at most this many bits is summed by key
+                                         // in LDS (a dense leaf), whatever its size
+constexpr int kDenseTile = 32768;        // records of a dense leaf per block of partial sums (larger leaves)
+constexpr int kDenseSlotWords = (1 << kDenseBits) + (1 << kDenseBits) / 64;  // sums + presence bits
 
 // Value forms.
 enum Form : int32_t {
@@ -106,12 +110,17 @@ struct Job {
 };
 
 // A range of records reduced by one finishing block.
-enum LeafKind : int32_t { kLeafSort = 0, kLeafPure = 1 };
+//   kLeafSort   at most kCap records: LDS radix sort (or sort-free ranks) and segmented sums
+//   kLeafPure   one key, more than kCap records: partial sums of kPureTile records, combined
+//   kLeafDense  relative keys of 1..kDenseBits bits, more than kCap records: sums by key in LDS;
+//               larger than kDenseTile records: per-block partial sums by key, combined
+enum LeafKind : int32_t { kLeafSort = 0, kLeafPure = 1, kLeafDense = 2 };
 struct Leaf {
   long long start;
   long long size;
   unsigned long long base;  // smallest key of the leaf: relative keys are key - base
-  long long ptile0;         // pure leaves: first partial
+  long long ptile0;         // pure / dense leaves: first partial tile
+  long long pslot;          // dense leaves: first word of the partial slots in the dense pool
   int32_t nptiles;
   int32_t tensor;
   int32_t kind;
@@ -119,6 +128,13 @@ struct Leaf {
   int32_t bits;             // bits of the relative keys
   int32_t pad;
 };
+
+// Words of one dense-leaf partial slot: 2^bits FP64 sums, then the presence
+// bits of the keys (one u32 per 32 keys, rounded up to whole u64 words).
+__host__ __device__ inline long long dense_slot_words(int bits) {
+  const long long nk = 1ll << bits;
+  return nk + (nk + 63) / 64;
+}
 
 // Device-side counters, zeroed by the init kernel of every call.
 struct Ctrl {
@@ -131,13 +147,14 @@ struct Ctrl {
   long long total;        // records over all tensors
   int32_t bm_done;        // bitmap blocks finished (the last one scans the block sums)
   int32_t pad;
+  unsigned long long dwords;  // words of the dense pool handed out
 };
 
 // Byte offsets of every region inside the caller's workspace.
 struct Layout {
   size_t ctrl, desc, jobs, tiles, table, starts, leaves, ordered, status;
-  size_t bitmap, wordpre, blockpre, partials, ptile_leaf, recA, recB, end;
-  long long jcap, tcap, lcap, pcap, words, wblocks;
+  size_t bitmap, wordpre, blockpre, partials, ptile_leaf, dpool, recA, recB, end;
+  long long jcap, tcap, lcap, pcap, words, wblocks, dpcap;
   int32_t count, levels;
 };
 

@@ -51,6 +51,9 @@ struct WsView {
   __device__ __forceinline__ unsigned* blockpre() const { return reinterpret_cast<unsigned*>(b + L.blockpre); }
   __device__ __forceinline__ double* partials() const { return reinterpret_cast<double*>(b + L.partials); }
   __device__ __forceinline__ int* ptile_leaf() const { return reinterpret_cast<int*>(b + L.ptile_leaf); }
+  __device__ __forceinline__ unsigned long long* dpool() const {
+    return reinterpret_cast<unsigned long long*>(b + L.dpool);
+  }
   __device__ __forceinline__ Rec* rec(int src) const {
     return reinterpret_cast<Rec*>(b + (src == kSrcA ? L.recA : L.recB));
   }
@@ -81,9 +84,27 @@ extern "C" int ttv_debug_phases_reset() {
   unsigned long long z[16] = {0};
   return (int)hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z));
 }
+#define TTV_COUNT(i) \
+  if (threadIdx.x == 0) atomicAdd(&g_phase[i], 1ull);
+__device__ unsigned long long g_phase2[16];
+#define TTV_PHASE2(i)                                            \
+  if (threadIdx.x == 0) {                                        \
+    const unsigned long long ph_n = wall_clock64();              \
+    atomicAdd(&g_phase2[i], ph_n - ph_t);                        \
+    ph_t = ph_n;                                                 \
+  }
+extern "C" int ttv_debug_phases2(unsigned long long* out) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase2), sizeof(g_phase2));
+}
+extern "C" int ttv_debug_phases2_reset() {
+  unsigned long long z[16] = {0};
+  return (int)hipMemcpyToSymbol(HIP_SYMBOL(g_phase2), z, sizeof(z));
+}
 #else
 #define TTV_PHASE_DECL
 #define TTV_PHASE(i)
+#define TTV_COUNT(i)
+#define TTV_PHASE2(i)
 #endif
 
 constexpr unsigned long long kFlagAgg = 1ull << 62;
@@ -269,6 +290,7 @@ __global__ __launch_bounds__(256) void k_init(WsView W, TDesc d0, const TDesc* d
     C->ticket = 0;
     C->bm_done = 0;
     C->error = 0;
+    C->dwords = 0;
   }
   // level-1 jobs (one per nonempty tensor) and their tiles, in tensor order:
   // job and first-tile offsets from block scans over chunks of 256 tensors
@@ -572,7 +594,7 @@ struct ClassifySmem {
 // bucket starts itself).  NT threads, kNDig/NT digits per thread.
 template <int NT>
 __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int Tnext, int maxlevel, int j, int slice, int slices,
-                              ClassifySmem& sm) {
+                              int dense_bits, ClassifySmem& sm) {
   constexpr int DPT = kNDig / NT;
   unsigned* s_start = sm.s_start;
   int* s_nb = sm.s_nb;
@@ -660,38 +682,54 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
     // buckets), handed out in digit order.
     const int dstb = dst_of(level);
     const bool deeper = J.shift > 0 && level + 1 <= maxlevel;
-    unsigned c_lj = 0, c_tile = 0, c_pure = 0;  // c_lj: leaves (low 16 bits), jobs (high 16 bits)
+    // a bucket too large for a leaf is split again at the next level unless
+    // its keys span at most dense_bits bits: then it is one dense leaf
+    // (kLeafPure when the key is fully fixed)
+    const bool split = J.shift > dense_bits;
+    const int dslot = (J.shift > 0 && !split) ? (int)dense_slot_words(J.shift) : 0;
+    unsigned c_lj = 0, c_tile = 0, c_pure = 0, c_dw = 0;  // c_lj: leaves (low 16 bits), jobs (high 16 bits)
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int d = tid * DPT + q;
       if (d < dlo || d >= dhi || !(s_cls[d] & 4)) continue;
       const unsigned szd = s_start[d + 1] - s_start[d];
-      if ((s_cls[d] & 3) == 3 && J.shift > 0) {
+      if ((s_cls[d] & 3) == 3 && split) {
         if (deeper) {
           c_lj += 1u << 16;
           c_tile += (unsigned)(((unsigned long long)szd + Tnext - 1) / Tnext);
         }
       } else {
         c_lj += 1u;
-        if ((s_cls[d] & 3) == 3) c_pure += (unsigned)(((unsigned long long)szd + kPureTile - 1) / kPureTile);
+        if ((s_cls[d] & 3) == 3) {
+          if (J.shift == 0) {
+            c_pure += (unsigned)(((unsigned long long)szd + kPureTile - 1) / kPureTile);
+          } else {
+            const unsigned nt = (unsigned)(((unsigned long long)szd + kDenseTile - 1) / kDenseTile);
+            c_pure += nt;
+            c_dw += nt * (unsigned)dslot;
+          }
+        }
       }
     }
-    __shared__ long long s_base[4];
-    unsigned t_lj, t_tile, t_pure;
+    __shared__ long long s_base[5];
+    unsigned t_lj, t_tile, t_pure, t_dw;
     unsigned o_lj = block_excl_scan<NT>(c_lj, wsum, t_lj);
     unsigned o_tile = block_excl_scan<NT>(c_tile, wsum, t_tile);
     unsigned o_pure = block_excl_scan<NT>(c_pure, wsum, t_pure);
+    unsigned o_dw = block_excl_scan<NT>(c_dw, wsum, t_dw);
     if (tid == 0) {
       s_base[0] = (t_lj & 0xffffu) ? atomicAdd(&C->nleaves, (int)(t_lj & 0xffffu)) : 0;
       s_base[1] = (t_lj >> 16) ? atomicAdd(&C->njobs[level + 1], (int)(t_lj >> 16)) : 0;
       s_base[2] = t_tile ? atomicAdd(&C->ntiles[level + 1], (int)t_tile) : 0;
       s_base[3] = t_pure ? atomicAdd(&C->npure, (int)t_pure) : 0;
+      s_base[4] = t_dw ? (long long)atomicAdd(&C->dwords, (unsigned long long)t_dw) : 0;
     }
     __syncthreads();
     long long nlid = s_base[0] + (o_lj & 0xffffu);
     long long njid = s_base[1] + (o_lj >> 16);
     long long nt0 = s_base[2] + o_tile;
     long long np0 = s_base[3] + o_pure;
+    long long ndw = s_base[4] + o_dw;
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int d = tid * DPT + q;
@@ -700,7 +738,7 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
       const unsigned long long dbase = J.prefix | ((unsigned long long)d << J.shift);
       const int cls = s_cls[d] & 3;
       const unsigned szd = s_start[d + 1] - s_start[d];
-      if (cls == 3 && J.shift > 0) {
+      if (cls == 3 && split) {
         const long long size = szd;
         if (!deeper) {
           set_error(C, TTV_E_DEVICE);
@@ -723,10 +761,11 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
           N.size = 0;
         }
         // digit bits of the new job: enough for sub-buckets of about kSmall
-        // records, but at least what the levels after it cannot take
+        // records, but at least what the levels after it (and a dense
+        // leaf) cannot take
         {
           const int after = maxlevel - (level + 1);
-          const int need = J.shift - kRMax * after;
+          const int need = J.shift - kRMax * after - dense_bits;
           int rs = 1;
           while (rs < kRMax && (size >> rs) > kSmall) ++rs;
           int r = rs > need ? rs : need;
@@ -754,9 +793,10 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
       Lf.src = dstb;
       Lf.ptile0 = 0;
       Lf.nptiles = 0;
+      Lf.pslot = 0;
       Lf.pad = 0;
       Lf.kind = kLeafSort;
-      if (cls == 3) {  // single key, too large for one block: pure leaf
+      if (cls == 3 && J.shift == 0) {  // single key, too large for one block: pure leaf
         Lf.size = szd;
         Lf.kind = kLeafPure;
         Lf.bits = 0;
@@ -769,6 +809,23 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
         }
         Lf.ptile0 = p0;
         Lf.nptiles = np;
+      } else if (cls == 3) {  // at most dense_bits key bits: summed by key
+        Lf.size = szd;
+        Lf.kind = kLeafDense;
+        Lf.bits = J.shift;
+        // partial sums by key per kDenseTile records, formed before the
+        // finishing pass (which then knows the leaf's distinct keys at once)
+        const int np = (int)((Lf.size + kDenseTile - 1) / kDenseTile);
+        const long long p0 = np0, w0 = ndw;
+        np0 += np;
+        ndw += (long long)np * dslot;
+        if (p0 + np > W.L.pcap || w0 + (long long)np * dslot > W.L.dpcap) {
+          set_error(C, TTV_E_DEVICE);
+          continue;
+        }
+        Lf.ptile0 = p0;
+        Lf.nptiles = np;
+        Lf.pslot = w0;
       } else if (cls == 2) {
         Lf.size = szd;
         Lf.bits = J.shift;
@@ -782,7 +839,7 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
         continue;
       }
       W.leaves()[lid] = Lf;
-      if (Lf.kind == kLeafPure) {
+      if (Lf.nptiles > 0) {
         int* pl = W.ptile_leaf();
         for (int k = 0; k < Lf.nptiles; ++k) pl[Lf.ptile0 + k] = (int)lid;
       }
@@ -826,7 +883,7 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
     const int njobs = clampi(C->njobs[level], W.L.jcap);
     for (long long it = blockIdx.x; it < (long long)njobs * slices; it += gc) {
       classify_item<kScatterThreads>(W, C, level, Tnext, maxlevel, (int)(it / slices), (int)(it % slices), slices,
-                                     cs);
+                                     PM == kPipePerm ? 0 : kDenseBits, cs);
       __syncthreads();
     }
     return;
@@ -981,18 +1038,91 @@ __global__ __launch_bounds__(256) void k_bitmap(WsView W) {
   }
 }
 
-// Pure leaves: partial sums of kPureTile records each (combined in FP64 by
-// the finishing pass); then every leaf is placed at its rank (key order).
-template <int F>
-__global__ __launch_bounds__(256) void k_leaves(WsView W) {
+// One partial tile of a dense leaf: the FP64 sums by relative key of up to
+// kDenseTile records (FP32 payloads: the exact pair, widened) and the
+// presence bits of the keys, written to the tile's slot in the dense pool.
+// Records are added in order: waves take turns over contiguous slices, a
+// wave's items in order, and same-entry lanes of one ds_add_f64 in lane
+// order (as in the sort-free leaves).  Without values (segment maps) only
+// the presence bits are formed.
+constexpr int kLeavesThreads = 256;
+constexpr int kLeavesIPT = 8;
+template <int F, int PM>
+__device__ __forceinline__ void dense_tile(WsView W, const Leaf& Lf, int p, double* sums, unsigned* pres) {
+  using FO = FormOps<F>;
+  constexpr int NW = kLeavesThreads / 64;
+  constexpr int RN = kLeavesThreads * kLeavesIPT;
+  const int tid = threadIdx.x, w = tid >> 6;
+  const unsigned ln = lane_id();
+  const int nk = 1 << Lf.bits, words = (nk + 31) >> 5;
+  if (PM == kPipeTTV)
+    for (int q = tid; q < nk; q += kLeavesThreads) sums[q] = 0.0;
+  for (int q = tid; q < words; q += kLeavesThreads) pres[q] = 0u;
+  __syncthreads();
+  const long long b = (long long)(p - Lf.ptile0) * kDenseTile;
+  const long long e = (Lf.size - b < (long long)kDenseTile) ? Lf.size : b + kDenseTile;
+  const gptr<const u64x2> R = to_global(reinterpret_cast<const u64x2*>(W.rec(Lf.src))) + Lf.start;
+  const unsigned kmask = (unsigned)nk - 1u;
+  for (long long rb = b; rb < e; rb += RN) {
+    unsigned k[kLeavesIPT];
+    double v[kLeavesIPT];
+#pragma unroll
+    for (int j = 0; j < kLeavesIPT; ++j) {
+      const long long i = rb + (long long)w * 64 * kLeavesIPT + j * 64 + ln;
+      k[j] = 0xffffffffu;
+      v[j] = 0.0;
+      if (i < e) {
+        const u64x2 rc = R[i];
+        k[j] = (unsigned)(rc.x - Lf.base) & kmask;
+        if (PM == kPipeTTV) v[j] = FO::to_f64(FO::from_pay(rc.y));
+        atomicOr(&pres[k[j] >> 5], 1u << (k[j] & 31u));
+      }
+    }
+    if (PM == kPipeTTV) {
+      for (int turn = 0; turn < NW; ++turn) {
+        if (w == turn) {
+#pragma unroll
+          for (int j = 0; j < kLeavesIPT; ++j)
+            if (k[j] != 0xffffffffu) atomicAdd(&sums[k[j]], v[j]);
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  gptr<unsigned long long> slot =
+      to_global(W.dpool()) + Lf.pslot + (long long)(p - Lf.ptile0) * dense_slot_words(Lf.bits);
+  if (PM == kPipeTTV)
+    for (int q = tid; q < nk; q += kLeavesThreads) slot[q] = (unsigned long long)__double_as_longlong(sums[q]);
+  gptr<unsigned> sp = (gptr<unsigned>)(slot + nk);
+  for (int q = tid; q < words; q += kLeavesThreads) sp[q] = pres[q];
+  __syncthreads();
+}
+
+// Pure leaves: partial sums of kPureTile records each; dense leaves larger
+// than kDenseTile records: partial sums by key per kDenseTile records (both
+// combined in FP64 by the finishing pass).  Then every leaf is placed at its
+// rank (key order).
+template <int F, int PM>
+__global__ __launch_bounds__(kLeavesThreads) void k_leaves(WsView W) {
   using FO = FormOps<F>;
   using Acc = typename FO::Acc;
   __shared__ Acc red[256];
+  __shared__ double s_sums[1 << kDenseBits];
+  __shared__ unsigned s_pres[(1 << kDenseBits) / 32];
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int np = clampi(C->npure, W.L.pcap);
   for (int p = blockIdx.x; p < np; p += gridDim.x) {
     const Leaf Lf = W.leaves()[W.ptile_leaf()[p]];
+    if (Lf.kind == kLeafDense) {
+      if (PM == kPipePerm || Lf.bits < 1 || Lf.bits > kDenseBits) {  // excluded by classification
+        if (threadIdx.x == 0) set_error(C, TTV_E_DEVICE);
+        continue;
+      }
+      dense_tile<F, PM>(W, Lf, p, s_sums, s_pres);
+      continue;
+    }
     const long long b = (long long)(p - Lf.ptile0) * kPureTile;
     const long long e = (Lf.size - b < (long long)kPureTile) ? Lf.size : b + kPureTile;
     const Rec* R = W.rec(Lf.src) + Lf.start;
@@ -1057,16 +1187,10 @@ __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit,
           s = kFlagInc;
           break;
         }
-#ifdef TTV_PHASE_PROFILE
-        atomicAdd(&g_phase[9], 1ull);
-#endif
         __builtin_amdgcn_s_sleep(1);
       }
     }
     const uint64_t pm = ballot((s >> 62) == 2);
-#ifdef TTV_PHASE_PROFILE
-    if (ln == 0) atomicAdd(&g_phase[8], 1ull);
-#endif
     const int stop = pm ? __ffsll((long long)pm) - 1 : 63;
     long long v = ((int)ln <= stop) ? (long long)(s & kValMask) : 0;
 #pragma unroll
@@ -1168,6 +1292,78 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     const gptr<const Rec> R = to_global(static_cast<const Rec*>(W.rec(Lf.src))) + Lf.start;
     const gptr<const u64x2> Rv = to_global(reinterpret_cast<const u64x2*>(W.rec(Lf.src))) + Lf.start;
     const int n = (int)(Lf.size < (long long)kCap ? Lf.size : (long long)kCap);
+    if (Lf.kind == kLeafDense) {
+      // ---- dense leaf: the partial slots of k_leaves (sums by relative key,
+      // at most kDenseBits bits, and presence bits) added up in tile order;
+      // the distinct keys are known before any sum, so the leaf's count is
+      // published at once; present keys written in key order ----
+      const int nk = 1 << Lf.bits, words = (nk + 31) >> 5;
+      const unsigned kmask = (unsigned)nk - 1u;
+      double* sums = reinterpret_cast<double*>(spay);  // kCap >= 2^kDenseBits entries
+      unsigned* pres = cnt;
+      unsigned* wpre = cnt + (1 << kDenseBits) / 32;
+      if (PM == kPipePerm || Lf.bits < 1 || Lf.bits > kDenseBits || Lf.size <= 0 || Lf.nptiles < 1) {
+        // excluded by classification
+        if (tid == 0) {
+          set_error(C, TTV_E_DEVICE);
+          publish(S, r, kFlagInc);
+        }
+        __syncthreads();
+        continue;
+      }
+      const long long slotw = dense_slot_words(Lf.bits);
+      const gptr<const unsigned long long> slots = to_global((const unsigned long long*)W.dpool()) + Lf.pslot;
+      {
+        for (int q = tid; q < words; q += NT) {
+          unsigned m = 0u;
+          for (int t = 0; t < Lf.nptiles; ++t) m |= ((const gptr<const unsigned>)(slots + t * slotw + nk))[q];
+          pres[q] = m;
+        }
+        __syncthreads();
+      }
+      // distinct keys: popcount prefix of the presence words (at most NT words)
+      unsigned u = 0;
+      {
+        const unsigned c = tid < words ? (unsigned)__popc(pres[tid]) : 0u;
+        const unsigned ex = block_excl_scan<NT>(c, wsum, u);
+        if (tid < words) wpre[tid] = ex;
+      }
+      if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);
+      if (PM == kPipeTTV && Lf.nptiles > 0) {  // the slots' sums, tile by tile
+        for (int q = tid; q < nk; q += NT) {
+          double a = 0.0;
+          for (int t = 0; t < Lf.nptiles; ++t) a += __longlong_as_double((long long)slots[t * slotw + q]);
+          sums[q] = a;
+        }
+      }
+      if (w == 0) {
+        const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
+        if (ln == 0) {
+          if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u));
+          s_prefix = prefix;
+          if (last && out_nnz) *out_nnz = prefix + u;
+        }
+      }
+      __syncthreads();
+      const long long prefix = s_prefix;
+      if (PM == kPipeTTV) {
+        for (int q = tid; q < nk; q += NT) {
+          const unsigned pw = pres[q >> 5], bit = 1u << (q & 31);
+          if (pw & bit) O.write(prefix + wpre[q >> 5] + (unsigned)__popc(pw & (bit - 1u)), Lf.base + q, sums[q]);
+        }
+      } else if (PM == kPipeSegMap) {
+        for (long long i = tid; i < Lf.size; i += NT) {
+          const u64x2 rc = Rv[i];
+          const unsigned kk = (unsigned)(rc.x - Lf.base) & kmask;
+          const unsigned pw = pres[kk >> 5];
+          seg_out[(long long)rc.y] = (int32_t)(prefix + wpre[kk >> 5] + (unsigned)__popc(pw & ((1u << (kk & 31)) - 1u)));
+        }
+      }
+      __syncthreads();
+      TTV_PHASE(10)
+      TTV_COUNT(13)
+      continue;
+    }
     if (Lf.kind != kLeafPure && (Lf.size > kCap || Lf.size <= 0)) {  // excluded by classification
       if (tid == 0) {
         set_error(C, TTV_E_DEVICE);
@@ -1207,6 +1403,8 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         }
       }
       __syncthreads();
+      TTV_PHASE(11)
+      TTV_COUNT(14)
       continue;
     }
     // ---- LDS radix sort of the relative keys.  Wave w holds the contiguous
@@ -1275,6 +1473,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         // (a leaf of few distinct keys is sorted instead: its in-order adds
         // would pile many lanes of one atomic onto one row)
         if (keep_pre && u_early >= 64u) {
+          TTV_PHASE2(0)
           // ---- sort-free leaf: every record knows its output row (the rank
           // of its key); each row's sum is built in FP64 at the position of
           // its first record, the others adding in leaf order (waves in
@@ -1299,6 +1498,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
             }
           }
           __syncthreads();
+          TTV_PHASE2(1)
           bool dup[IPT];
           double pv[IPT];  // the record's product in FP64
 #pragma unroll
@@ -1329,6 +1529,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           } else {
             __syncthreads();
           }
+          TTV_PHASE2(2)
           if (w == 0) {
             const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early);
             if (ln == 0) {
@@ -1338,10 +1539,14 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
             }
           }
           __syncthreads();
+          TTV_PHASE2(3)
           const long long prefix = s_prefix;
           for (int q = tid; q < (int)u_early; q += NT)
             O.write(prefix + q, Lf.base + rkey[q], acc[firstpos[q]]);
           __syncthreads();
+          TTV_PHASE2(4)
+          TTV_PHASE(7)
+          TTV_COUNT(12)
           continue;
         }
       }
@@ -1570,6 +1775,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     }
     __syncthreads();
     TTV_PHASE(6)
+    TTV_COUNT(15)
   }
 }
 
@@ -1607,7 +1813,7 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
-  hipLaunchKernelGGL(k_leaves<F>, dim3(2 * cus), dim3(256), 0, s, W);
+  hipLaunchKernelGGL((k_leaves<F, PM>), dim3(4 * cus), dim3(kLeavesThreads), 0, s, W);
   prof_begin(TTV_PROF_FINISH, s);
   hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(2 * cus), dim3(kFinishThreads), 0, s, W, P.spin_limit);
   prof_end(TTV_PROF_FINISH, s);

@@ -62,10 +62,14 @@ def test_plan_key_layout():
     assert list(info.bits[:2]) == [7, 7]
     # mixed-radix key: first remaining mode most significant, range 100 * 80
     assert list(info.stride[:2]) == [80, 1] and info.key_bits == 13
+    # bucket levels: after the first digit, 12-bit digits until at most 12
+    # key bits remain (such buckets are summed by key, whatever their size)
     rc, info = _query(_desc((10_000,) * 3, 10_000_000), [0])
-    assert rc == 0 and info.key_bits == 27 and info.digit1_bits == 12
+    assert rc == 0 and info.key_bits == 27 and info.digit1_bits == 12 and info.levels == 2
     rc, info = _query(_desc((2000,) * 4, 50_000_000), [1])
-    assert rc == 0 and info.key_bits == 33 and info.levels >= 3
+    assert rc == 0 and info.key_bits == 33 and info.levels == 2
+    rc, info = _query(_desc((1200,) * 3, 17_280_000), [1])
+    assert rc == 0 and info.key_bits == 21 and info.digit1_bits == 12 and info.levels == 1
     rc, info = _query(_desc((1, 50, 1), 100), [1])
     assert rc == 0 and info.key_bits == 0 and info.levels == 1
     assert info.workspace_bytes > 0
@@ -132,9 +136,8 @@ def test_reuse_plan_host_checks():
         chunks = nnz // 512 + 1
         base = nnz * 8 + nnz * 4 + nnz // 8
         assert base <= nd.value <= base + chunks * (8 + 2 * 16 + 2 * 8) + 7 * 256
-        ws_pipe = ctypes.c_size_t(0)
-        assert lib.ttv_coo_workspace(ctypes.byref(d), 1, 0, ctypes.byref(ws_pipe)) == 0
-        assert nw.value >= ws_pipe.value + 8 * nnz  # the pipeline, then the permutation and rows
+        # the sorting pipeline (two 16-byte record buffers), then the permutation and rows
+        assert nw.value >= 2 * 16 * nnz + 8 * nnz
         v = ctypes.c_void_p(1)
         # apply before setup; setup with buffers too small: rejected before anything is enqueued
         assert lib.ttv_reuse_apply(plan, v, 10_000, v, None) == E["ARG"]

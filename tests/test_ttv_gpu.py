@@ -236,12 +236,13 @@ def test_wide_keys_over_32_bits():
 
 
 def test_zipf_deeper_levels():
-    """1e6 Zipf nonzeros: heavy first-level buckets split at two more levels."""
+    """1e6 Zipf nonzeros: heavy first-level buckets split at a second level,
+    whose large buckets (at most 12 key bits) are summed by key."""
     P = _api()
     X, mode, v = synth.workload_zipf(scale=0.02)
     subs, vals, gv_ = to_gpu(X, v)
     info = P.plan_query(subs, vals, X.shape, [mode])
-    assert info.levels >= 3
+    assert info.levels == 2
     say("zipf 1e6 c32")
     gs, gv, _ = P.ttv(subs, vals, X.shape, mode, gv_, out_f64=True)
     check_ttv(X, mode, v, gs, gv, C32_TOL, "zipf 1e6")
