@@ -500,10 +500,14 @@ def only_run(name, K, W):
               else P.AllButOp(subs, vals, X.shape, 0, [None, gv[1], gv[2]]))
         fn = op.launch
     elif name == "batch":
+        # with TTV_TUNE_CACHE naming an existing autotuner cache the plan takes
+        # its tuning from there (no tuning launches to profile)
+        cache = os.environ.get("TTV_TUNE_CACHE")
         ms = synth.workload_batch(count=512)
         B = P.BatchedTTV([(torch.from_numpy(m.X.subs).cuda(), torch.from_numpy(m.X.vals).cuda(), m.X.shape,
-                           m.mode, torch.from_numpy(m.v).cuda()) for m in ms])
-        B.autotune()
+                           m.mode, torch.from_numpy(m.v).cuda()) for m in ms], tune_cache=cache)
+        if not (cache and os.path.exists(cache)):
+            B.autotune()
         fn = B.launch
     elif name in ("grad_fwd", "grad_bwd"):
         G, keep, gvecs, target = synth.workload_grad()
