@@ -24,6 +24,7 @@ namespace {
 constexpr size_t kHdr = 256;                  // error word lives here (same offset as Ctrl::error)
 constexpr size_t kLdsBudget = 150 * 1024;     // dynamic LDS of one dense block
 constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr size_t kMaxWavesPerCU = 32;         // gfx950: 8 waves per SIMD, 4 SIMDs
 constexpr int kTile = kDenseThreads * kDenseIPT;
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -57,7 +58,9 @@ void finish_pass(Pass& p, long long nnz) {
     p.acc_total += p.nk[q];
   }
   p.lds = acc + p.tile;
-  const int bpc = (int)std::max<size_t>(1, std::min<size_t>(4, kLdsPerCU / std::max<size_t>(p.lds, 1)));
+  // blocks per CU: LDS-limited, and at most kMaxWavesPerCU / 16 waves of a block
+  const int bpc = (int)std::max<size_t>(
+      1, std::min<size_t>(kMaxWavesPerCU / (kDenseThreads / 64), kLdsPerCU / std::max<size_t>(p.lds, 1)));
   const long long ntiles = std::max<long long>(1, (nnz + kTile - 1) / kTile);
   p.grid = (int)std::max<long long>(1, std::min<long long>((long long)kAssumedCUs * bpc, ntiles));
 }

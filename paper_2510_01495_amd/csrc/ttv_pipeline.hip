@@ -1170,33 +1170,60 @@ __device__ __forceinline__ void publish(unsigned long long* S, int r, unsigned l
 // are read again.
 __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit, Ctrl* C,
                                    unsigned long long early = 0) {
+  // Each step reads kLookG groups of 64 predecessors, their loads in flight
+  // together (lane l of group g reads predecessor base - 64 g - l).  The
+  // groups are then resolved nearest first: a lane waits only while its
+  // status is unpublished and no inclusive prefix lies between it and this
+  // leaf, and the walk stops at the group holding the nearest inclusive
+  // prefix (the first leaf of a tensor of a batch publishes one at once, so
+  // statuses beyond it may still be unpublished and are never waited for).
+  constexpr int kLookG = 4;
   const unsigned ln = lane_id();
   long long prefix = 0;
-  for (int base = r - 1;; base -= 64) {
-    const int j = base - (int)ln;
-    unsigned long long s = kFlagInc;  // before the first leaf: an inclusive prefix of 0
-    if (j >= 0) {
-      int spins = 0;
-      s = base == r - 1 ? early : 0ull;
-      for (;;) {
-        if (s >> 62) break;
-        s = __hip_atomic_load(&S[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (s >> 62) break;
-        if (++spins > spin_limit) {
-          set_error(C, TTV_E_DEVICE);
-          s = kFlagInc;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+  for (int base = r - 1;; base -= 64 * kLookG) {
+    unsigned long long s[kLookG];
+#pragma unroll
+    for (int g = 0; g < kLookG; ++g) {
+      const int j = base - 64 * g - (int)ln;
+      s[g] = kFlagInc;  // before the first leaf: an inclusive prefix of 0
+      if (j >= 0) {
+        s[g] = (base == r - 1 && g == 0) ? early : 0ull;
+        if (!(s[g] >> 62)) s[g] = __hip_atomic_load(&S[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    const uint64_t pm = ballot((s >> 62) == 2);
-    const int stop = pm ? __ffsll((long long)pm) - 1 : 63;
-    long long v = ((int)ln <= stop) ? (long long)(s & kValMask) : 0;
+    long long v = 0;
+    bool found = false;
+#pragma unroll
+    for (int g = 0; g < kLookG; ++g) {
+      const int j = base - 64 * g - (int)ln;
+      int spins = 0;
+      uint64_t pm;
+      int stop;
+      for (;;) {
+        pm = ballot((s[g] >> 62) == 2);
+        stop = pm ? __ffsll((long long)pm) - 1 : 63;
+        const bool need = (int)ln <= stop && j >= 0 && !(s[g] >> 62);
+        if (!ballot(need)) break;
+        if (need) {
+          if (++spins > spin_limit) {
+            set_error(C, TTV_E_DEVICE);
+            s[g] = kFlagInc;
+          } else {
+            __builtin_amdgcn_s_sleep(1);
+            s[g] = __hip_atomic_load(&S[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+      v += ((int)ln <= stop) ? (long long)(s[g] & kValMask) : 0;
+      if (pm) {
+        found = true;
+        break;  // wave-uniform
+      }
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     prefix += v;
-    if (pm) break;
+    if (found) break;
   }
   return prefix;
 }
@@ -1257,10 +1284,16 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
   constexpr int NT = kFinishThreads;
   constexpr int IPT = kFinishIPT;
   constexpr int NW = NT / 64;
-  constexpr int MAXD = 9;  // widest LDS digit
-  __shared__ unsigned sk[kCap];
-  __shared__ unsigned short si[kCap];
-  __shared__ uint64_t spay[kCap];  // payloads in leaf order (no second read of the records)
+  constexpr int MAXD = 8;  // widest LDS digit
+  // Region A holds, by leaf kind: the sort's relative keys and positions
+  // (sk, si); a sort-free leaf's row sums and row keys (acc, rkey); a dense
+  // leaf's sums by key (acc).  With the digit counters (cnt) the block
+  // needs about 49 KB of LDS, so three blocks share a CU.
+  __shared__ __attribute__((aligned(16))) unsigned char smA[kCap * 8 + kCap * 2];
+  unsigned* const sk = reinterpret_cast<unsigned*>(smA);
+  unsigned short* const si = reinterpret_cast<unsigned short*>(smA + kCap * 4);
+  double* const acc = reinterpret_cast<double*>(smA);
+  unsigned short* const rkey = reinterpret_cast<unsigned short*>(smA + kCap * 8);
   __shared__ unsigned cnt[NW << MAXD];
   __shared__ unsigned wsum[NW];
   __shared__ Seg<F> wagg[NW];
@@ -1299,7 +1332,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       // published at once; present keys written in key order ----
       const int nk = 1 << Lf.bits, words = (nk + 31) >> 5;
       const unsigned kmask = (unsigned)nk - 1u;
-      double* sums = reinterpret_cast<double*>(spay);  // kCap >= 2^kDenseBits entries
+      double* sums = acc;  // kCap >= 2^kDenseBits entries
       unsigned* pres = cnt;
       unsigned* wpre = cnt + (1 << kDenseBits) / 32;
       if (PM == kPipePerm || Lf.bits < 1 || Lf.bits > kDenseBits || Lf.size <= 0 || Lf.nptiles < 1) {
@@ -1415,15 +1448,17 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     const int nj = (n + 64 * NW - 1) / (64 * NW);
     unsigned k[IPT];
     unsigned ix[IPT];
+    uint64_t pl[IPT];  // the items' payloads (sorted leaves read them again after the sort)
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const int i = w * 64 * nj + j * 64 + (int)ln;
       ix[j] = (unsigned)i;
       k[j] = 0;
+      pl[j] = 0;
       if (j < nj) {
         const u64x2 rc = Rv[i < n ? i : n - 1];  // whole records: one coalesced 16-byte read per item
         k[j] = (unsigned)(rc.x - Lf.base);
-        if (i < n) spay[i] = rc.y;
+        pl[j] = rc.y;
       }
     }
     TTV_PHASE(1)
@@ -1473,56 +1508,47 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         // (a leaf of few distinct keys is sorted instead: its in-order adds
         // would pile many lanes of one atomic onto one row)
         if (keep_pre && u_early >= 64u) {
-          TTV_PHASE2(0)
           // ---- sort-free leaf: every record knows its output row (the rank
-          // of its key); each row's sum is built in FP64 at the position of
-          // its first record, the others adding in leaf order (waves in
-          // turn, items in order, same-entry lanes of one ds_add_f64 in lane
-          // order), so the sum is the in-order sum, bitwise repeatable.  An
-          // FP32 record's payload is its exact product pair, widened to FP64
-          // (no rounding before the sum). ----
-          unsigned* firstpos = sk;  // per row: leaf position of its first record
-          unsigned short* rkey = si;  // per row: its relative key (bits <= 16 here)
-          double* acc = reinterpret_cast<double*>(spay);
-          for (int q = tid; q < (int)u_early; q += NT) firstpos[q] = 0xffffffffu;
+          // of its key on the bitmap); each row's sum is built in FP64 from
+          // 0, its records adding in leaf order (waves in turn, items in
+          // order, same-entry lanes of one ds_add_f64 in lane order), so the
+          // sum is the in-order sum, bitwise repeatable.  A leaf whose keys
+          // are all distinct stores each product directly.  An FP32 record's
+          // payload is its exact product pair, widened to FP64 (no rounding
+          // before the sum).  Every record writes its row's key (the same
+          // value for all records of a row). ----
+          TTV_PHASE2(0)
+          const bool dups = u_early < (unsigned)n;
+          if (dups)
+            for (int q = tid; q < (int)u_early; q += NT) acc[q] = 0.0;
           __syncthreads();  // also orders the prefix words before their reads
           unsigned row[IPT];
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) {
-            const int i = w * 64 * nj + j * 64 + (int)ln;
-            row[j] = 0;
-            if (j < nj && i < n) {
-              const unsigned kk = k[j], wi = kk >> 5;
-              row[j] = cnt[words + wi] + (unsigned)__popc(cnt[wi] & ((1u << (kk & 31u)) - 1u));
-              atomicMin(&firstpos[row[j]], (unsigned)i);
-            }
-          }
-          __syncthreads();
-          TTV_PHASE2(1)
-          bool dup[IPT];
           double pv[IPT];  // the record's product in FP64
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
             const int i = w * 64 * nj + j * 64 + (int)ln;
-            dup[j] = false;
+            row[j] = 0xffffffffu;
             pv[j] = 0.0;
             if (j < nj && i < n) {
-              pv[j] = FO::to_f64(FO::from_pay(spay[i]));
-              if (firstpos[row[j]] == (unsigned)i) {
-                rkey[row[j]] = (unsigned short)k[j];
-                if constexpr (F != kF64) acc[i] = pv[j];  // the row's sum starts as its first product
+              const unsigned kk = k[j], wi = kk >> 5;
+              row[j] = cnt[words + wi] + (unsigned)__popc(cnt[wi] & ((1u << (kk & 31u)) - 1u));
+              pv[j] = FO::to_f64(FO::from_pay(pl[j]));
+              if (row[j] < u_early) {  // always: the rank of a present key
+                rkey[row[j]] = (unsigned short)kk;
+                if (!dups) acc[row[j]] = pv[j];
               } else {
-                dup[j] = true;
+                set_error(C, TTV_E_DEVICE);
+                row[j] = 0xffffffffu;
               }
             }
           }
-          if (u_early < (unsigned)n) {  // some key repeats: in-order adds
-            if constexpr (F != kF64) __syncthreads();  // the first products are in place
+          TTV_PHASE2(1)
+          if (dups) {  // some key repeats: in-order adds
             for (int turn = 0; turn < NW; ++turn) {
               if (w == turn) {
 #pragma unroll
                 for (int j = 0; j < IPT; ++j)
-                  if (dup[j]) atomicAdd(&acc[firstpos[row[j]]], pv[j]);
+                  if (row[j] != 0xffffffffu) atomicAdd(&acc[row[j]], pv[j]);
               }
               __syncthreads();
             }
@@ -1541,8 +1567,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           __syncthreads();
           TTV_PHASE2(3)
           const long long prefix = s_prefix;
-          for (int q = tid; q < (int)u_early; q += NT)
-            O.write(prefix + q, Lf.base + rkey[q], acc[firstpos[q]]);
+          for (int q = tid; q < (int)u_early; q += NT) O.write(prefix + q, Lf.base + rkey[q], acc[q]);
           __syncthreads();
           TTV_PHASE2(4)
           TTV_PHASE(7)
@@ -1694,7 +1719,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       for (int j = 0; j < IPT; ++j) {
         const int p = pw + j * 64 + (int)ln;
         pay[j] = 0;
-        if (j < nj) pay[j] = spay[si[p < n ? p : n - 1]];
+        if (j < nj) pay[j] = Rv[si[p < n ? p : n - 1]].y;  // records are L2-resident: read at the start of the leaf
       }
       Acc c = FO::zero();  // value of the segment open at the end of the previous round
 #pragma unroll
@@ -1748,12 +1773,12 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       if (p < n) {
         const long long rowi = prefix + hrun + upto - 1;
         if (PM == kPipeSegMap) {
-          seg_out[(long long)spay[si[p]]] = (int32_t)rowi;
+          seg_out[(long long)Rv[si[p]].y] = (int32_t)rowi;
         } else if (PM == kPipePerm) {
           // sorted position -> nonzero and output row; the run's last record
           // writes the row's coordinates
           const long long pos = Lf.start - D.base + p;
-          to_global(D.perm_out)[pos] = (int32_t)spay[si[p]];
+          to_global(D.perm_out)[pos] = (int32_t)Rv[si[p]].y;
           seg_out[pos] = (int32_t)rowi;
           const bool end = p == n - 1 || (wide ? R[si[p + 1]].key != R[si[p]].key : sk[p + 1] != sk[p]);
           if (end) O.write_subs(rowi, wide ? R[si[p]].key : Lf.base + sk[p]);
@@ -1815,7 +1840,8 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
   hipLaunchKernelGGL((k_leaves<F, PM>), dim3(4 * cus), dim3(kLeavesThreads), 0, s, W);
   prof_begin(TTV_PROF_FINISH, s);
-  hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(2 * cus), dim3(kFinishThreads), 0, s, W, P.spin_limit);
+  // three blocks per CU: the finish needs about 49 KB of LDS per block
+  hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(3 * cus), dim3(kFinishThreads), 0, s, W, P.spin_limit);
   prof_end(TTV_PROF_FINISH, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
