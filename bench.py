@@ -444,6 +444,47 @@ def cfg_reuse(X, subs, vals, v, K):
             **roof(alg, t["mean_ms"]), "k_reuse_apply_us": kms * 1e3, "max_rel_err_sampled": err}
 
 
+def cfg_sparse_adjoint(X, subs, vals, v, mode=0):
+    """The sparse product's adjoint on the 1e7 tensor (mode 0): the forward
+    that keeps every nonzero's output row (ttv_coo_save) against plain
+    ttv_coo, and the adjoint that reads those rows against the one that
+    sorts again.  Adjoint bytes: indices, value and row of every nonzero,
+    grad_out gathered, grad_vals written, the vector and its gradient."""
+    import numpy as np
+    import torch
+    import paper_2510_01495_amd as P
+    from paper_2510_01495_amd import _lib as L
+    fwd = P.TTVOp(subs, vals, X.shape, [mode], [v])
+    sav = P.TTVSaveOp(subs, vals, X.shape, mode, v)
+    fwd.launch()
+    sav.launch()
+    gs, gvl, _, seg = sav.result()
+    nout = int(gs.shape[0])
+    g = torch.from_numpy(np.random.default_rng(21).standard_normal(nout)).cuda()
+    vv = [None] * len(X.shape)
+    vv[mode] = v
+    b_re = P.BackwardOp(subs, vals, X.shape, "sparse", mode, vv)
+    b_sv = P.BackwardOp(subs, vals, X.shape, "sparse", mode, vv, seg=seg)
+    b_re.launch(g)
+    b_sv.launch(g)
+    torch.cuda.synchronize()
+    L.check(b_re.device_error(), "device")
+    L.check(b_sv.device_error(), "device")
+    same = bool(torch.equal(b_re.grad_vecs[mode], b_sv.grad_vecs[mode])
+                and torch.equal(b_re.grad_vals, b_sv.grad_vals))
+    t_f = time_calls(fwd.launch)
+    t_s = time_calls(sav.launch)
+    t_br = time_calls(lambda: b_re.launch(g))
+    t_bs = time_calls(lambda: b_sv.launch(g))
+    d = len(X.shape)
+    alg_b = X.nnz * (d * 8 + 8 + 4 + 8 + 8) + 2 * X.shape[mode] * 8
+    return {"mode": mode, "nnz_out": nout, "ttv_coo": t_f, "ttv_coo_save": t_s,
+            "save_over_plain": t_s["mean_ms"] / t_f["mean_ms"],
+            "backward_resort": t_br, "backward_saved": t_bs, **roof(alg_b, t_bs["mean_ms"]),
+            "fwd_plus_bwd_ms": {"resort": t_f["mean_ms"] + t_br["mean_ms"], "saved": t_s["mean_ms"] + t_bs["mean_ms"]},
+            "saved_equals_resort_bitwise": same}
+
+
 def cfg_mttkrp(X, subs, vals, K, R=16, mode=0):
     """Sparse MTTKRP on the 1e7 tensor (mode 0, R = 16 U[0,1) factor columns):
     setup once, then applies.  HBM bytes per apply: value, two 32-bit indices
@@ -650,6 +691,7 @@ def main():
         cfg["uniform_1e7"] = uni
         log("uniform done")
         cfg["plan_reuse"] = cfg_reuse(X, subs, vals, gvu[0], K)
+        cfg["sparse_adjoint"] = cfg_sparse_adjoint(X, subs, vals, gvu[0])
         cfg["mttkrp"] = cfg_mttkrp(X, subs, vals, K)
         del X, subs, vals, gvu
         torch.cuda.empty_cache()

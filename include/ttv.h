@@ -281,6 +281,35 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep,
                      void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Sparse product and adjoint with the grouping kept between them.  Eq. 3 is
+ * linear in v and in vals, so the adjoint of the sparse form needs, for
+ * every nonzero e, only row(e): the output row its product is summed into.
+ *   ttv_coo_save   ttv_coo in one mode (same arguments, coordinates and
+ *                  count; values formed by the sorting pipeline, bitwise
+ *                  ttv_coo's wherever ttv_coo sorts, within the rounding
+ *                  bound of its small by-key paths) that also writes
+ *                  seg[e] = row(e), device int32, nnz entries.  Every
+ *                  record's nonzero index travels with it through the sort
+ *                  (4 more bytes per record and level).  TTV_DROP_ZEROS is
+ *                  refused (TTV_E_ARG): seg names rows before any removal.
+ *   ttv_coo_backward_saved  the TTV_BWD_SPARSE adjoint of ttv_coo_backward
+ *                  (same arguments and results) with row(e) read from seg
+ *                  instead of recomputed by a second sort: one pass over
+ *                  the nonzeros.  seg must be what ttv_coo_save wrote for
+ *                  the same X and mode; its entries are not checked.
+ * ---------------------------------------------------------------------- */
+int ttv_coo_save_workspace(const ttv_coo_desc* X, int32_t mode, int32_t flags, size_t* bytes);
+int ttv_coo_save(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len,
+                 void* out_subs, void* out_vals, int64_t* out_nnz, int32_t* seg,
+                 void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+int ttv_coo_backward_saved_workspace(const ttv_coo_desc* X, int32_t mode, int32_t flags,
+                                     size_t* bytes);
+int ttv_coo_backward_saved(const ttv_coo_desc* X, int32_t mode, const void* const* vecs,
+                           const int64_t* vec_lens, const int32_t* seg, const void* grad_out,
+                           void* const* grad_vecs, void* grad_vals,
+                           void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched sparse TTV: `count` independent tensors, each with its own mode
  * and vector, all run by one fixed sequence of persistent kernels.  A plan
  * binds the tensors, vectors and outputs (all device pointers stay fixed) so

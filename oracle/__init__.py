@@ -28,6 +28,7 @@ from .ttv_oracle import (  # noqa: F401
     ttv,
     ttv_coords,
     ttv_plain,
+    ttv_rows,
     ttv_scaled,
     ttv_entries,
     ttv_vjp,

@@ -417,6 +417,16 @@ def _segment_of(subs, shape, mode, newsubs) -> np.ndarray:
     return seg
 
 
+def ttv_rows(subs, shape, mode) -> np.ndarray:
+    """row(e) of every nonzero (Sec. 3.3, Eq. 3): the position of its
+    remaining-mode index tuple among the distinct tuples in lexicographic
+    order -- the output entry its product is summed into."""
+    subs = np.asarray(subs)
+    if subs.shape[0] == 0:
+        return np.zeros(0, dtype=np.int64)
+    return _segment_of(subs, shape, mode, ttv_coords(subs, shape, mode)).astype(np.int64)
+
+
 def ttv_vjp(subs, vals, shape, mode, v, grad_out):
     """Adjoint of the sparse TTV, from the linearity of Eq. 3 in x and in a.
 

@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     TTVAllButFunction,
     TTVFunction,
     TTVOp,
+    TTVSaveOp,
     coo_desc,
     mttkrp,
     plan_query,
@@ -24,10 +25,13 @@ from .api import (  # noqa: F401
     ttv_allbut,
     ttv_allbut_noalloc,
     ttv_backward,
+    ttv_backward_saved,
     ttv_full,
     ttv_multi,
     ttv_pyttb,
+    ttv_save,
 )
 
-__all__ = ["AllButOp", "BackwardOp", "BatchedTTV", "FullOp", "MTTKRP", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp", "coo_desc",
-           "mttkrp", "plan_query", "ttv", "ttv_allbut", "ttv_allbut_noalloc", "ttv_backward", "ttv_full", "ttv_multi", "ttv_pyttb"]
+__all__ = ["AllButOp", "BackwardOp", "BatchedTTV", "FullOp", "MTTKRP", "ReuseTTV", "TTVAllButFunction", "TTVFunction", "TTVOp",
+           "TTVSaveOp", "coo_desc", "mttkrp", "plan_query", "ttv", "ttv_allbut", "ttv_allbut_noalloc", "ttv_backward",
+           "ttv_backward_saved", "ttv_full", "ttv_multi", "ttv_pyttb", "ttv_save"]

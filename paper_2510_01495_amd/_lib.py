@@ -64,6 +64,13 @@ SIGNATURES = {
     "ttv_coo_backward": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_void_p), POINTER(c_int64),
                                    c_void_p, POINTER(c_void_p), c_void_p, c_void_p, c_size_t, c_int32,
                                    c_void_p]),
+    "ttv_coo_save_workspace": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_size_t)]),
+    "ttv_coo_save": (c_int32, [POINTER(CooDesc), c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
+    "ttv_coo_backward_saved_workspace": (c_int32, [POINTER(CooDesc), c_int32, c_int32, POINTER(c_size_t)]),
+    "ttv_coo_backward_saved": (c_int32, [POINTER(CooDesc), c_int32, POINTER(c_void_p), POINTER(c_int64),
+                                         c_void_p, c_void_p, POINTER(c_void_p), c_void_p, c_void_p, c_size_t,
+                                         c_int32, c_void_p]),
     "ttv_batch_plan_create": (c_int32, [c_int32, POINTER(CooDesc), POINTER(c_int32), POINTER(c_void_p),
                                         POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_int32, c_char_p,
                                         POINTER(c_void_p)]),

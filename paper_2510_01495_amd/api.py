@@ -133,6 +133,58 @@ def ttv(subs, vals, shape, mode: int, v, *, flags: int = 0, out_f64: bool = Fals
     return op.result()
 
 
+class TTVSaveOp:
+    """``ttv`` in one mode that also keeps, for every nonzero, the output row
+    its product is summed into (``seg``, int32): what the adjoint needs, so
+    that ``ttv_backward_saved`` does not sort again."""
+
+    def __init__(self, subs, vals, shape, mode: int, v, *, flags: int = 0, out_f64: bool = False):
+        self.lib = L.load()
+        self.subs, self.vals, self.shape, self.mode = subs, vals, tuple(int(s) for s in shape), int(mode)
+        self.v = v.contiguous()
+        _check_tensor(self.v, "v")
+        if self.v.dtype != vals.dtype:
+            raise TypeError("v must have the dtype of vals")
+        self.flags = flags | (L.OUT_F64 if out_f64 else 0)
+        self.desc = coo_desc(subs, vals, self.shape)
+        d, nnz = len(self.shape), subs.shape[0]
+        nb = c_size_t(0)
+        L.check(self.lib.ttv_coo_save_workspace(byref(self.desc), self.mode, self.flags, byref(nb)),
+                "ttv_coo_save_workspace")
+        dev = subs.device
+        self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=dev)
+        self.out_subs = torch.empty((max(nnz, 1), d - 1), dtype=subs.dtype, device=dev)
+        self.out_vals = torch.empty(max(nnz, 1), dtype=_out_value_dtype(vals, out_f64), device=dev)
+        self.out_nnz = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.seg = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        self.nnz = nnz
+        self.newshape = tuple(s for j, s in enumerate(self.shape) if j != self.mode)
+
+    def launch(self):
+        rc = self.lib.ttv_coo_save(byref(self.desc), self.mode, self.v.data_ptr() if self.v.numel() else None,
+                                   self.v.numel(), self.out_subs.data_ptr(), self.out_vals.data_ptr(),
+                                   self.out_nnz.data_ptr(), self.seg.data_ptr(), self.ws.data_ptr(),
+                                   self.ws.numel(), self.flags, _stream(self.subs.device))
+        L.check(rc, "ttv_coo_save")
+
+    def device_error(self) -> int:
+        return self.lib.ttv_check_device_error(self.ws.data_ptr(), _stream(self.subs.device))
+
+    def result(self):
+        """(newsubs, newvals, newshape, seg) after synchronising."""
+        L.check(self.device_error(), "device")
+        m = int(self.out_nnz.item())
+        return self.out_subs[:m], self.out_vals[:m], self.newshape, self.seg[:self.nnz]
+
+
+def ttv_save(subs, vals, shape, mode: int, v, *, flags: int = 0, out_f64: bool = False):
+    """``ttv`` plus the output row of every nonzero: returns (newsubs,
+    newvals, newshape, seg)."""
+    op = TTVSaveOp(subs, vals, shape, mode, v, flags=flags, out_f64=out_f64)
+    op.launch()
+    return op.result()
+
+
 def ttv_pyttb(subs, vals, shape, mode: int, v, *, out_f64: bool = False):
     """The product as the pyttb procedure of Sec. 3.3 returns it: output
     entries whose sum is exactly zero are removed, and a result with more
@@ -324,14 +376,38 @@ def ttv_backward(subs, vals, shape, kind: str, mode: int, vecs, grad_out, *, wan
     return gv, (gvals[:vals.numel()] if gvals is not None else None)
 
 
+def ttv_backward_saved(subs, vals, shape, mode: int, v, seg, grad_out, *, want_vec: bool = True,
+                       want_vals: bool = True, flags: int = 0):
+    """Adjoint of ``ttv`` in ``mode`` from the rows ``seg`` that ``ttv_save``
+    kept (no second sort).  Returns (grad_v or None, grad_vals or None)."""
+    op = BackwardOp(subs, vals, shape, "sparse", mode, _one_vec(v, mode, len(shape)), seg=seg,
+                    want_vecs=[mode] if want_vec else [], want_vals=want_vals, flags=flags)
+    op.launch(grad_out.contiguous())
+    L.check(op.device_error(), "device")
+    return op.grad_vecs[mode], (op.grad_vals[:vals.numel()] if op.grad_vals is not None else None)
+
+
+def _one_vec(v, mode, d):
+    vv = [None] * d
+    vv[mode] = v
+    return vv
+
+
 class BackwardOp:
     """A planned adjoint (as ``ttv_backward``) with preallocated gradients and
     workspace; ``launch(grad_out)`` enqueues it without synchronising."""
 
     def __init__(self, subs, vals, shape, kind: str, mode: int, vecs, *, want_vecs=None, want_vals: bool = True,
-                 flags: int = 0):
+                 flags: int = 0, seg=None):
         if kind not in ("sparse", "allbut"):
             raise ValueError("kind must be 'sparse' or 'allbut'")
+        if seg is not None:
+            if kind != "sparse":
+                raise ValueError("a saved row map belongs to the sparse form")
+            _check_tensor(seg, "seg")
+            if seg.dtype != torch.int32 or not seg.is_contiguous() or seg.numel() < subs.shape[0]:
+                raise ValueError("seg must be a contiguous int32 tensor with one row per nonzero")
+        self.seg = seg
         self.lib = L.load()
         self.subs, self.vals, self.shape, self.mode = subs, vals, tuple(int(s) for s in shape), int(mode)
         d = len(self.shape)
@@ -354,18 +430,29 @@ class BackwardOp:
         self.grad_vals = torch.empty(max(1, vals.numel()), dtype=vals.dtype, device=dev) if want_vals else None
         self.flags = flags
         nb = c_size_t(0)
-        L.check(self.lib.ttv_coo_backward_workspace(byref(self.desc), self.kind, self.mode, flags, byref(nb)),
-                "ttv_coo_backward_workspace")
+        if seg is None:
+            L.check(self.lib.ttv_coo_backward_workspace(byref(self.desc), self.kind, self.mode, flags, byref(nb)),
+                    "ttv_coo_backward_workspace")
+        else:
+            L.check(self.lib.ttv_coo_backward_saved_workspace(byref(self.desc), self.mode, flags, byref(nb)),
+                    "ttv_coo_backward_saved_workspace")
         self.ws = torch.empty(max(1, nb.value), dtype=torch.uint8, device=dev)
 
     def launch(self, grad_out):
         if grad_out.dtype != self.vals.dtype or not grad_out.is_contiguous():
             raise TypeError("grad_out must be contiguous with the dtype of vals")
-        rc = self.lib.ttv_coo_backward(byref(self.desc), self.kind, self.mode, self.c_vecs, self.c_lens,
-                                       grad_out.data_ptr() if grad_out.numel() else None, self.gptrs,
-                                       self.grad_vals.data_ptr() if self.grad_vals is not None else None,
-                                       self.ws.data_ptr(), self.ws.numel(), self.flags, _stream(self.subs.device))
-        L.check(rc, "ttv_coo_backward")
+        gptr = grad_out.data_ptr() if grad_out.numel() else None
+        gvals = self.grad_vals.data_ptr() if self.grad_vals is not None else None
+        if self.seg is None:
+            rc = self.lib.ttv_coo_backward(byref(self.desc), self.kind, self.mode, self.c_vecs, self.c_lens, gptr,
+                                           self.gptrs, gvals, self.ws.data_ptr(), self.ws.numel(), self.flags,
+                                           _stream(self.subs.device))
+            L.check(rc, "ttv_coo_backward")
+        else:
+            rc = self.lib.ttv_coo_backward_saved(byref(self.desc), self.mode, self.c_vecs, self.c_lens,
+                                                 self.seg.data_ptr(), gptr, self.gptrs, gvals, self.ws.data_ptr(),
+                                                 self.ws.numel(), self.flags, _stream(self.subs.device))
+            L.check(rc, "ttv_coo_backward_saved")
 
     def device_error(self) -> int:
         return self.lib.ttv_check_device_error(self.ws.data_ptr(), _stream(self.subs.device))
@@ -399,21 +486,20 @@ class TTVFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, subs, vals, shape, mode, v):
-        ns, nv, _ = ttv(subs, vals, shape, mode, v)
+        # the forward keeps the output row of every nonzero, so the backward
+        # does not sort again
+        ns, nv, _, seg = ttv_save(subs, vals, shape, mode, v)
         ctx.shape, ctx.mode = tuple(shape), int(mode)
-        ctx.save_for_backward(subs, vals, v)
+        ctx.save_for_backward(subs, vals, v, seg)
         ctx.mark_non_differentiable(ns)
         return nv, ns
 
     @staticmethod
     def backward(ctx, gvals_out, _gs):
-        subs, vals, v = ctx.saved_tensors
-        vecs = [None] * len(ctx.shape)
-        vecs[ctx.mode] = v
-        gv, gvals = ttv_backward(subs, vals, ctx.shape, "sparse", ctx.mode, vecs, gvals_out.to(vals.dtype),
-                                 want_vecs=[ctx.mode] if ctx.needs_input_grad[4] else [],
-                                 want_vals=ctx.needs_input_grad[1])
-        return None, gvals, None, None, gv[ctx.mode]
+        subs, vals, v, seg = ctx.saved_tensors
+        gv, gvals = ttv_backward_saved(subs, vals, ctx.shape, ctx.mode, v, seg, gvals_out.to(vals.dtype),
+                                       want_vec=ctx.needs_input_grad[4], want_vals=ctx.needs_input_grad[1])
+        return None, gvals, None, None, gv
 
 
 class BatchedTTV:

@@ -175,7 +175,8 @@ static int levels_of(const TDesc& D, int dense_bits) {
   return std::min(kMaxLevels, levels);
 }
 
-Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1, bool dense) {
+Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1, bool dense,
+                   bool aux) {
   Layout L{};
   L.count = count;
   L.levels = levels;
@@ -212,6 +213,8 @@ Layout make_layout(long long total, int count, int levels, int T1, int T2, long 
   L.dpool = take((size_t)L.dpcap * sizeof(unsigned long long));
   L.recA = take((size_t)total * sizeof(Rec));
   L.recB = take(levels > 1 ? (size_t)total * sizeof(Rec) : 0);
+  L.auxA = take(aux ? (size_t)total * sizeof(int32_t) : 0);
+  L.auxB = take(aux && levels > 1 ? (size_t)total * sizeof(int32_t) : 0);
   L.end = o;
   return L;
 }
@@ -230,7 +233,8 @@ int finish_plan(PipePlan& P) {
   P.T1 = choose_T1(P.total);
   P.T2 = 16384;
   P.tiles1 = (P.total + P.T1 - 1) / P.T1;
-  P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1, dense_bits_of(P.pipe_mode) > 0);
+  P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1, dense_bits_of(P.pipe_mode) > 0,
+                    P.pipe_mode == kPipeTTVSeg);
   return TTV_OK;
 }
 
@@ -368,6 +372,47 @@ int ttv_coo(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len, v
   const void* vecs[1] = {v};
   const int64_t lens[1] = {v_len};
   return ttv_coo_multi(X, 1, &mode, vecs, lens, out_subs, out_vals, out_nnz, ws, ws_bytes, flags, stream);
+}
+
+int ttv_coo_save_workspace(const ttv_coo_desc* X, int32_t mode, int32_t flags, size_t* bytes) {
+  if (!bytes) return TTV_E_NULL;
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;  // the saved rows are the rows before any removal
+  PipePlan P;
+  const int rc = plan_single(X, 1, &mode, flags, kPipeTTVSeg, P);
+  if (rc) return rc;  // (nnz above 2^31 - 1 is refused there: rows and indices fit int32)
+  *bytes = P.L.end;
+  return TTV_OK;
+}
+
+int ttv_coo_save(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_len, void* out_subs, void* out_vals,
+                 int64_t* out_nnz, int32_t* seg, void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;
+  PipePlan P;
+  int rc = plan_single(X, 1, &mode, flags, kPipeTTVSeg, P);
+  if (rc) return rc;
+  if (!out_nnz) return TTV_E_NULL;
+  if (v_len != X->shape[mode]) return TTV_E_SHAPE;
+  if (X->nnz > 0 && (!v || !out_subs || !out_vals || !seg)) return TTV_E_NULL;
+  if (!ws || ws_bytes < P.L.end) return TTV_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  P.d0.vec[mode] = v;
+  P.d0.out_subs = out_subs;
+  P.d0.out_vals = out_vals;
+  P.d0.out_nnz = reinterpret_cast<long long*>(out_nnz);
+  P.d0.seg_out = seg;
+  P.cus = device_cus();
+  if (X->nnz == 0) {  // no leaf would write the count: a zero count and a clear error word
+    (void)hipGetLastError();
+    launch_zero(out_nnz, sizeof(int64_t), s);
+    launch_zero(ws, sizeof(Ctrl), s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_last_hip_error((int)e);
+      return TTV_E_HIP;
+    }
+    return TTV_OK;
+  }
+  return launch_pipeline(P, ws, s);
 }
 
 int ttv_profile_events(int32_t kernel, void* const* starts, void* const* stops, int32_t capacity) {

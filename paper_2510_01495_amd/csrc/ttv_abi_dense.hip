@@ -293,6 +293,34 @@ int scratch_address(void** out) {
   return TTV_OK;
 }
 
+// The sparse form's adjoint from the output row of every nonzero (seg):
+// grad_v of the contracted mode keyed by its index (dense passes, or the
+// sorting pipeline for a mode too long for LDS) and grad_vals per nonzero.
+int sparse_adjoint(const ttv_coo_desc* X, int mode, const void* const* vecs, const int32_t* seg,
+                   const void* grad_out, void* const* grad_vecs, void* grad_vals, const Pass* passes, int npass,
+                   const int* fb, int nfb, const DenseWs& W, char* w, int flags, int idx64, int form, int out_f64,
+                   hipStream_t s) {
+  int rc;
+  for (int i = 0; i < nfb; ++i) {
+    const void* nofac[TTV_MAX_ORDER] = {nullptr};
+    rc = run_fallback(X, fb[i], flags, nofac, grad_out, seg, grad_vecs[fb[i]], out_f64, w, W.pipe_off, W.tmp_off,
+                      s);
+    if (rc) return rc;
+  }
+  DenseArgs A;
+  dense_base(X, flags, A);
+  A.fac[mode] = vecs[mode];
+  A.gseg = grad_out;
+  A.seg = seg;
+  for (int p = 0; p < npass; ++p) {
+    void* outs[kDenseMaxAcc] = {nullptr, nullptr, nullptr, nullptr};
+    for (int q = 0; q < passes[p].nacc; ++q) outs[q] = grad_vecs[passes[p].mode[q]];
+    rc = run_pass(passes[p], A, w, W.part_off, outs, grad_vals, idx64, form, out_f64, s);
+    if (rc) return rc;
+  }
+  return TTV_OK;
+}
+
 }  // namespace
 
 }  // namespace ttv
@@ -499,28 +527,61 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, 
     rc = launch_pipeline(P, w + W.pipe_off, s);
     if (rc) return rc;
     // 2. grad_v keyed by the contracted mode, grad_vals per nonzero
-    const void* fac[TTV_MAX_ORDER] = {nullptr};
-    fac[mode] = vecs[mode];
-    for (int i = 0; i < nfb; ++i) {
-      const void* nofac[TTV_MAX_ORDER] = {nullptr};
-      rc = run_fallback(X, fb[i], flags, nofac, grad_out, seg, grad_vecs[fb[i]], out_f64, w, W.pipe_off, W.tmp_off,
-                        s);
-      if (rc) return rc;
-    }
-    DenseArgs A;
-    dense_base(X, flags, A);
-    for (int j = 0; j < X->order; ++j) A.fac[j] = fac[j];
-    A.gseg = grad_out;
-    A.seg = seg;
-    for (int p = 0; p < npass; ++p) {
-      void* outs[kDenseMaxAcc] = {nullptr, nullptr, nullptr, nullptr};
-      for (int q = 0; q < passes[p].nacc; ++q) outs[q] = grad_vecs[passes[p].mode[q]];
-      rc = run_pass(passes[p], A, w, W.part_off, outs, grad_vals, idx64, form, out_f64, s);
-      if (rc) return rc;
-    }
+    rc = sparse_adjoint(X, mode, vecs, seg, grad_out, grad_vecs, grad_vals, passes, npass, fb, nfb, W, w, flags,
+                        idx64, form, out_f64, s);
+    if (rc) return rc;
   } else {
     return TTV_E_ARG;
   }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_last_hip_error((int)e);
+    return TTV_E_HIP;
+  }
+  return TTV_OK;
+}
+
+int ttv_coo_backward_saved_workspace(const ttv_coo_desc* X, int32_t mode, int32_t flags, size_t* bytes) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;
+  if (!bytes) return TTV_E_NULL;
+  int form, idx64;
+  int rc = check_common(X, mode, form, idx64);
+  if (rc) return rc;
+  Pass passes[TTV_MAX_ORDER];
+  int npass, fb[TTV_MAX_ORDER], nfb;
+  plan_passes(X, &mode, 1, true, passes, npass, fb, nfb);
+  *bytes = layout_dense(X, flags, passes, npass, fb, nfb, 0, false).total;
+  return TTV_OK;
+}
+
+int ttv_coo_backward_saved(const ttv_coo_desc* X, int32_t mode, const void* const* vecs, const int64_t* vec_lens,
+                           const int32_t* seg, const void* grad_out, void* const* grad_vecs, void* grad_vals,
+                           void* ws, size_t ws_bytes, int32_t flags, ttv_stream_t stream) {
+  if (flags & TTV_DROP_ZEROS) return TTV_E_ARG;
+  int form, idx64;
+  int rc = check_common(X, mode, form, idx64);
+  if (rc) return rc;
+  if (!vecs || !vec_lens || !grad_vecs) return TTV_E_NULL;
+  if (vec_lens[mode] != X->shape[mode]) return TTV_E_SHAPE;
+  if (X->nnz > 0 && (!grad_out || !seg || !vecs[mode])) return TTV_E_NULL;
+  Pass wpasses[TTV_MAX_ORDER];
+  int wnp, wfb[TTV_MAX_ORDER], wnfb;
+  plan_passes(X, &mode, 1, true, wpasses, wnp, wfb, wnfb);  // what the workspace query sized
+  const DenseWs W = layout_dense(X, flags, wpasses, wnp, wfb, wnfb, 0, false);
+  if (!ws || ws_bytes < W.total) return TTV_E_WORKSPACE;
+  Pass passes[TTV_MAX_ORDER];
+  int npass, fb[TTV_MAX_ORDER], nfb;
+  int modes[1] = {mode};
+  plan_passes(X, modes, grad_vecs[mode] ? 1 : 0, grad_vals != nullptr, passes, npass, fb, nfb);
+  for (int p = 0; p < npass; ++p)
+    if (W.part_off + pass_ws(passes[p]) > W.total) return TTV_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
+  const int out_f64 = form == kF64 ? 1 : 0;
+  if (nfb == 0) launch_zero(ws, kHdr, s);  // the error word (a fallback's pipeline clears its own)
+  rc = sparse_adjoint(X, mode, vecs, seg, grad_out, grad_vecs, grad_vals, passes, npass, fb, nfb, W,
+                      static_cast<char*>(ws), flags, idx64, form, out_f64, s);
+  if (rc) return rc;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_last_hip_error((int)e);

@@ -35,7 +35,9 @@ int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags
 int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, int pipe_mode, PipePlan& P);
 // dense: buckets of at most kDenseBits relative key bits may become dense
 // leaves (every pipeline mode except kPipePerm, whose leaves must be sorted)
-Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1, bool dense);
+// aux: the nonzero-index arrays beside the record buffers (kPipeTTVSeg)
+Layout make_layout(long long total, int count, int levels, int T1, int T2, long long tiles1, bool dense,
+                   bool aux = false);
 inline int dense_bits_of(int pipe_mode) { return pipe_mode == kPipePerm ? 0 : kDenseBits; }
 int finish_plan(PipePlan& P);  // levels, tiles and layout of a planned single tensor
 int launch_zero(void* p, size_t bytes, hipStream_t s);

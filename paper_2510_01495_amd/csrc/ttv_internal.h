@@ -52,7 +52,13 @@ enum PipeMode : int32_t {
   kPipeSegMap = 1,  // no values: for every input nonzero, the output row it lands in
   kPipePerm = 2,    // no values: output coordinates, and for every sorted position the
                     // nonzero there (perm_out) and its output row (seg_out)
+  kPipeTTVSeg = 3,  // kPipeTTV, and for every input nonzero the output row it lands in
+                    // (seg_out): each record's nonzero index travels in a parallel
+                    // 4-byte array beside the record buffers
 };
+
+// Modes whose records carry products and whose leaves sum them.
+__host__ __device__ constexpr bool pm_values(int pm) { return pm == kPipeTTV || pm == kPipeTTVSeg; }
 
 struct Rec {
   uint64_t key;
@@ -67,7 +73,8 @@ struct TDesc {
   void* out_subs;               // (nnz_out, nrem) row-major, index dtype of the input
   void* out_vals;               // nnz_out values
   long long* out_nnz;           // device scalar
-  int32_t* seg_out;             // segment map (kPipeSegMap); output row per sorted position (kPipePerm)
+  int32_t* seg_out;             // output row per nonzero (kPipeSegMap, kPipeTTVSeg); per sorted
+                                // position (kPipePerm)
   int32_t* perm_out;            // nonzero per sorted position (kPipePerm)
   const void* segfac;           // optional factor of every payload, gathered through segidx
   const int32_t* segidx;
@@ -153,7 +160,7 @@ struct Ctrl {
 // Byte offsets of every region inside the caller's workspace.
 struct Layout {
   size_t ctrl, desc, jobs, tiles, table, starts, leaves, ordered, status;
-  size_t bitmap, wordpre, blockpre, partials, ptile_leaf, dpool, recA, recB, end;
+  size_t bitmap, wordpre, blockpre, partials, ptile_leaf, dpool, recA, recB, auxA, auxB, end;
   long long jcap, tcap, lcap, pcap, words, wblocks, dpcap;
   int32_t count, levels;
 };

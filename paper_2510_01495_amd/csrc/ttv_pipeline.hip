@@ -57,6 +57,10 @@ struct WsView {
   __device__ __forceinline__ Rec* rec(int src) const {
     return reinterpret_cast<Rec*>(b + (src == kSrcA ? L.recA : L.recB));
   }
+  // nonzero index of every record, beside rec(src) (kPipeTTVSeg)
+  __device__ __forceinline__ int32_t* aux(int src) const {
+    return reinterpret_cast<int32_t*>(b + (src == kSrcA ? L.auxA : L.auxB));
+  }
 };
 
 __device__ __forceinline__ int dst_of(int level) { return (level & 1) ? kSrcA : kSrcB; }
@@ -200,7 +204,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long lo
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const long long i = (long long)j * 64 + ln;
-    a[j] = (PM == kPipeTTV && i < nrec) ? vals[r0 + i] : (In)0;
+    a[j] = (pm_values(PM) && i < nrec) ? vals[r0 + i] : (In)0;
   }
   long long x[MO][IPT];
   fetch_cols<IdxT, F, IPT, MO>(S, r0, nrec, stage, x);
@@ -217,7 +221,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long lo
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     key[j] = 0;
-    pay[j] = PM != kPipeTTV ? (uint64_t)(r0 + (long long)j * 64 + ln) : FO::start_prod(a[j]);
+    pay[j] = !pm_values(PM) ? (uint64_t)(r0 + (long long)j * 64 + ln) : FO::start_prod(a[j]);
   }
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
@@ -228,7 +232,7 @@ __device__ __forceinline__ void load_round(const RawSrc<IdxT, F, MO>& S, long lo
       for (int j = 0; j < IPT; ++j) key[j] += (uint64_t)x[m][j] * st;
     }
   }
-  if (PM != kPipeTTV) return;
+  if (!pm_values(PM)) return;
   In g[MO][IPT];
 #pragma unroll
   for (int m = 0; m < MO; ++m) {
@@ -934,9 +938,15 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
     const long long roff = J.start - Dp->base + b;
     const RawSrc<IdxT, F, MO>& S = rsrc;
     gptr<u64x2> gdst = to_global((u64x2*)dst);
+    // kPipeTTVSeg: the records' nonzero indices move alongside them
+    const gptr<const int32_t> srcX =
+        (PM == kPipeTTVSeg && srcR) ? to_global((const int32_t*)W.aux(J.src)) + J.start + b : (gptr<const int32_t>)nullptr;
+    const gptr<int32_t> gaux =
+        PM == kPipeTTVSeg ? to_global(W.aux(dst_of(level))) + J.start : (gptr<int32_t>)nullptr;
     for (long long rb = 0; rb < n; rb += RN) {
       uint64_t key[IPT], pay[IPT];
       unsigned dg[IPT];
+      int32_t ax[IPT];
       {
         const long long i0 = rb + (long long)w * RW + ln;
         if (srcR) {
@@ -944,15 +954,19 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
           for (int j = 0; j < IPT; ++j) {
             key[j] = 0;
             pay[j] = 0;
+            ax[j] = 0;
             if (i0 + j * 64 < n) {
               const u64x2 r = srcR[i0 + j * 64];
               key[j] = r.x;
               pay[j] = r.y;
+              if (PM == kPipeTTVSeg) ax[j] = srcX[i0 + j * 64];
             }
           }
         } else {
           const long long s0 = rb + (long long)w * RW;
           load_round<IdxT, F, PM, IPT, MO>(S, roff + s0, n - s0, stage[w], C, key, pay);
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) ax[j] = (int32_t)(roff + i0 + j * 64);  // the nonzero's index in its tensor
         }
       }
       // positions: the waves take turns adding to the bucket cursors; in a
@@ -980,6 +994,7 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
           r.x = key[j];
           r.y = pay[j];
           gdst[pos[j]] = r;
+          if (PM == kPipeTTVSeg) gaux[pos[j]] = ax[j];
         }
       }
     }
@@ -1055,7 +1070,7 @@ __device__ __forceinline__ void dense_tile(WsView W, const Leaf& Lf, int p, doub
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
   const int nk = 1 << Lf.bits, words = (nk + 31) >> 5;
-  if (PM == kPipeTTV)
+  if (pm_values(PM))
     for (int q = tid; q < nk; q += kLeavesThreads) sums[q] = 0.0;
   for (int q = tid; q < words; q += kLeavesThreads) pres[q] = 0u;
   __syncthreads();
@@ -1074,11 +1089,11 @@ __device__ __forceinline__ void dense_tile(WsView W, const Leaf& Lf, int p, doub
       if (i < e) {
         const u64x2 rc = R[i];
         k[j] = (unsigned)(rc.x - Lf.base) & kmask;
-        if (PM == kPipeTTV) v[j] = FO::to_f64(FO::from_pay(rc.y));
+        if (pm_values(PM)) v[j] = FO::to_f64(FO::from_pay(rc.y));
         atomicOr(&pres[k[j] >> 5], 1u << (k[j] & 31u));
       }
     }
-    if (PM == kPipeTTV) {
+    if (pm_values(PM)) {
       for (int turn = 0; turn < NW; ++turn) {
         if (w == turn) {
 #pragma unroll
@@ -1092,7 +1107,7 @@ __device__ __forceinline__ void dense_tile(WsView W, const Leaf& Lf, int p, doub
   __syncthreads();
   gptr<unsigned long long> slot =
       to_global(W.dpool()) + Lf.pslot + (long long)(p - Lf.ptile0) * dense_slot_words(Lf.bits);
-  if (PM == kPipeTTV)
+  if (pm_values(PM))
     for (int q = tid; q < nk; q += kLeavesThreads) slot[q] = (unsigned long long)__double_as_longlong(sums[q]);
   gptr<unsigned> sp = (gptr<unsigned>)(slot + nk);
   for (int q = tid; q < words; q += kLeavesThreads) sp[q] = pres[q];
@@ -1362,7 +1377,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         if (tid < words) wpre[tid] = ex;
       }
       if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);
-      if (PM == kPipeTTV && Lf.nptiles > 0) {  // the slots' sums, tile by tile
+      if (pm_values(PM) && Lf.nptiles > 0) {  // the slots' sums, tile by tile
         for (int q = tid; q < nk; q += NT) {
           double a = 0.0;
           for (int t = 0; t < Lf.nptiles; ++t) a += __longlong_as_double((long long)slots[t * slotw + q]);
@@ -1379,17 +1394,20 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       }
       __syncthreads();
       const long long prefix = s_prefix;
-      if (PM == kPipeTTV) {
+      if (pm_values(PM)) {
         for (int q = tid; q < nk; q += NT) {
           const unsigned pw = pres[q >> 5], bit = 1u << (q & 31);
           if (pw & bit) O.write(prefix + wpre[q >> 5] + (unsigned)__popc(pw & (bit - 1u)), Lf.base + q, sums[q]);
         }
-      } else if (PM == kPipeSegMap) {
+      }
+      if (PM == kPipeSegMap || PM == kPipeTTVSeg) {  // every record's row: the rank of its key
+        const gptr<const int32_t> Xa = to_global((const int32_t*)W.aux(Lf.src)) + Lf.start;
         for (long long i = tid; i < Lf.size; i += NT) {
           const u64x2 rc = Rv[i];
           const unsigned kk = (unsigned)(rc.x - Lf.base) & kmask;
           const unsigned pw = pres[kk >> 5];
-          seg_out[(long long)rc.y] = (int32_t)(prefix + wpre[kk >> 5] + (unsigned)__popc(pw & ((1u << (kk & 31)) - 1u)));
+          const long long e = PM == kPipeSegMap ? (long long)rc.y : (long long)Xa[i];
+          seg_out[e] = (int32_t)(prefix + wpre[kk >> 5] + (unsigned)__popc(pw & ((1u << (kk & 31)) - 1u)));
         }
       }
       __syncthreads();
@@ -1415,7 +1433,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           double v = 0.0;
           const double* P = W.partials() + Lf.ptile0;
           for (int k = 0; k < Lf.nptiles; ++k) v += P[k];
-          if (PM == kPipeTTV) O.write(prefix, Lf.base, v);
+          if (pm_values(PM)) O.write(prefix, Lf.base, v);
           if (PM == kPipePerm) O.write_subs(prefix, Lf.base);
           if (last && out_nnz) *out_nnz = prefix + 1;
         }
@@ -1424,6 +1442,12 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         __syncthreads();
         const long long row = s_prefix;
         for (long long i = tid; i < Lf.size; i += NT) seg_out[(long long)R[i].pay] = (int32_t)row;
+      }
+      if (PM == kPipeTTVSeg) {
+        __syncthreads();
+        const long long row = s_prefix;
+        const gptr<const int32_t> Xa = to_global((const int32_t*)W.aux(Lf.src)) + Lf.start;
+        for (long long i = tid; i < Lf.size; i += NT) seg_out[(long long)Xa[i]] = (int32_t)row;
       }
       if (PM == kPipePerm) {  // every record of the run, in record order
         __syncthreads();
@@ -1504,7 +1528,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         const int jp = r - 1 - (int)ln;
         lb_early = jp >= 0 ? __hip_atomic_load(&S[jp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagInc;
       }
-      if constexpr (PM == kPipeTTV) {
+      if constexpr (pm_values(PM)) {
         // (a leaf of few distinct keys is sorted instead: its in-order adds
         // would pile many lanes of one atomic onto one row)
         if (keep_pre && u_early >= 64u) {
@@ -1568,6 +1592,14 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           TTV_PHASE2(3)
           const long long prefix = s_prefix;
           for (int q = tid; q < (int)u_early; q += NT) O.write(prefix + q, Lf.base + rkey[q], acc[q]);
+          if constexpr (PM == kPipeTTVSeg) {
+            const gptr<const int32_t> Xa = to_global((const int32_t*)W.aux(Lf.src)) + Lf.start;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+              const int i = w * 64 * nj + j * 64 + (int)ln;
+              if (j < nj && i < n && row[j] != 0xffffffffu) seg_out[(long long)Xa[i]] = (int32_t)(prefix + row[j]);
+            }
+          }
           __syncthreads();
           TTV_PHASE2(4)
           TTV_PHASE(7)
@@ -1713,7 +1745,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     TTV_PHASE(3)
     // ---- payloads and the segmented scan (rounds within the wave) ----
     Acc val[IPT];
-    if (PM == kPipeTTV) {
+    if (pm_values(PM)) {
       uint64_t pay[IPT];
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
@@ -1743,7 +1775,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       }
     }
     __syncthreads();
-    if (PM == kPipeTTV) {
+    if (pm_values(PM)) {
       // the segment open at the start of this wave continues from earlier waves
       Seg<F> cw;
       cw.f = 0;
@@ -1794,6 +1826,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
             const uint64_t key = wide ? R[si[p]].key : Lf.base + sk[p];
             O.write(rowi, key, FO::to_f64(val[j]));
           }
+          if (PM == kPipeTTVSeg) seg_out[(long long)to_global((const int32_t*)W.aux(Lf.src))[Lf.start + si[p]]] = (int32_t)rowi;
         }
       }
       hrun += (unsigned)__popcll(hm[j]);
@@ -1880,6 +1913,11 @@ int launch_pipeline(const PipePlan& P, void* ws, hipStream_t s) {
     if (P.form == kF64)
       return i64 ? launch_mo<long long, kF64, kPipeSegMap>(P, ws, s) : launch_mo<int, kF64, kPipeSegMap>(P, ws, s);
     return i64 ? launch_mo<long long, kC32, kPipeSegMap>(P, ws, s) : launch_mo<int, kC32, kPipeSegMap>(P, ws, s);
+  }
+  if (P.pipe_mode == kPipeTTVSeg) {
+    if (P.form == kF64)
+      return i64 ? launch_mo<long long, kF64, kPipeTTVSeg>(P, ws, s) : launch_mo<int, kF64, kPipeTTVSeg>(P, ws, s);
+    return i64 ? launch_mo<long long, kC32, kPipeTTVSeg>(P, ws, s) : launch_mo<int, kC32, kPipeTTVSeg>(P, ws, s);
   }
   if (P.form == kF64)
     return i64 ? launch_mo<long long, kF64, kPipeTTV>(P, ws, s) : launch_mo<int, kF64, kPipeTTV>(P, ws, s);

@@ -14,7 +14,10 @@ only where the exact value is 0).
     keeping mode 0, the gradients of the regression loss for both vectors and
     vals (oracle gradient, and FP64 central differences with h = 1e-6 on
     sampled coordinates), and the adjoint with only one vector's gradient
-    requested.
+    requested;
+  * the sparse product that keeps every nonzero's output row, on the 1e7
+    uniform tensor (with the adjoint from those rows) and on the 5e7 Zipf
+    tensor: all rows against the oracle's.
 
 Each test runs tens of seconds of oracle work on the host."""
 
@@ -212,3 +215,50 @@ def test_gradient_2e7_whole_and_finite_differences():
         d = (fd[0] - fd[1]) / (2 * h)
         grad = g_or[1][e]
         assert abs(d - grad) <= 1e-6 * abs(grad) + 8 * eps * L0 / h, (e, d, grad)
+
+
+def test_uniform_1e7_saved_rows_and_adjoint_whole():
+    """ttv_coo_save in mode 0 of the 1e7 uniform tensor: every nonzero's row
+    against the oracle's, values bitwise ttv_coo's; then the adjoint from
+    those rows (grad v and all 1e7 grad vals) against the oracle's."""
+    import torch
+    import paper_2510_01495_amd as P
+    X, vecs = synth.workload_uniform(scale=1.0)
+    subs, vals, v = _cuda(X.subs), _cuda(X.vals), _cuda(vecs[0])
+    say("full size uniform 1e7: ttv_save mode 0")
+    gs, gv, _, seg = P.ttv_save(subs, vals, X.shape, 0, v)
+    rows = oracle.ttv_rows(X.subs, X.shape, 0)
+    assert np.array_equal(seg.cpu().numpy().astype(np.int64), rows), "rows differ"
+    ts, tv, _ = P.ttv(subs, vals, X.shape, 0, v)
+    assert np.array_equal(ts.cpu().numpy(), gs.cpu().numpy())
+    assert np.array_equal(tv.cpu().numpy().view(np.uint64), gv.cpu().numpy().view(np.uint64))
+    g = np.random.default_rng(31).standard_normal(gs.shape[0])
+    say("adjoint from the saved rows")
+    gvec, gvals = P.ttv_backward_saved(subs, vals, X.shape, 0, v, seg, _cuda(g))
+    wv, wvals = oracle.ttv_vjp(X.subs, X.vals, X.shape, 0, vecs[0], g)
+    av, _ = oracle.ttv_vjp(X.subs, np.abs(X.vals), X.shape, 0, np.abs(vecs[0]), np.abs(g))
+    check_values(gvec.cpu().numpy(), wv, av, F64_TOL, "grad v", componentwise=False)
+    # grad_vals[e] = v[i_0(e)] * g[row(e)]: one rounded product, so exact
+    assert np.array_equal(gvals.cpu().numpy(), wvals)
+
+
+def test_zipf_5e7_saved_rows_whole():
+    """ttv_coo_save on the 5e7 Zipf tensor (FP64 form): all 5e7 rows against
+    the oracle's, coordinates and values bitwise ttv_coo's."""
+    import torch
+    import paper_2510_01495_amd as P
+    Z, mode, v = synth.workload_zipf()
+    zs, zv, zvec = _cuda(Z.subs.astype(np.int64)), _cuda(Z.vals.astype(np.float64)), _cuda(v.astype(np.float64))
+    say("full size Zipf 5e7: ttv_save")
+    op = P.TTVSaveOp(zs, zv, Z.shape, mode, zvec)
+    op.launch()
+    gs, gv, _, seg = op.result()
+    got = seg.cpu().numpy().astype(np.int64)
+    say("oracle rows")
+    assert np.array_equal(got, oracle.ttv_rows(Z.subs, Z.shape, mode)), "rows differ"
+    gs, gv = gs.cpu().numpy(), gv.cpu().numpy()
+    del op, seg
+    torch.cuda.empty_cache()
+    ts, tv, _ = P.ttv(zs, zv, Z.shape, mode, zvec)
+    assert np.array_equal(ts.cpu().numpy(), gs)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint64), gv.view(np.uint64))

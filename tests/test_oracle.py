@@ -746,3 +746,55 @@ def test_scaled_product_matches_its_parts(d, seed):
         _, wsc, _ = oracle.ttv(subs, np.abs(vals), dims, mode, np.abs(v))
         assert np.array_equal(ns, ws) and np.array_equal(nv, wv) and shp == wshp
         assert np.array_equal(sc, wsc)
+
+
+# --------------------------------------------------------------------------
+# row(e): the output row each nonzero's product is summed into
+# --------------------------------------------------------------------------
+# On the hand tensor (tuples listed with the rows ttv returns in HAND):
+#   mode 2 keeps (i, j): nonzeros 0..4 have (0,0) (0,1) (1,0) (1,1) (0,0)
+#   mode 0 keeps (j, k): (0,0) (1,0) (0,1) (1,1) (0,1)
+#   mode 1 keeps (i, k): (0,0) (0,0) (1,1) (1,1) (0,1)
+HAND_ROWS = {2: [0, 1, 2, 3, 0], 0: [0, 2, 1, 3, 1], 1: [0, 0, 2, 2, 1]}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_rows_hand_example(mode):
+    assert oracle.ttv_rows(HAND_SUBS, (2, 2, 2), mode).tolist() == HAND_ROWS[mode]
+
+
+@pytest.mark.parametrize("d,seed", CASES[::3])
+def test_rows_brute_force(d, seed):
+    """row(e) = the number of distinct remaining tuples lexicographically
+    below e's own (pure-Python comparison of tuples); every row is hit; the
+    row's coordinates are e's tuple; the same as numpy's unique inverse."""
+    X = _tiny(d, seed)
+    for mode in range(d):
+        rows = oracle.ttv_rows(X.subs, X.shape, mode)
+        R = [j for j in range(d) if j != mode]
+        tuples = [tuple(int(x) for x in X.subs[e, R]) for e in range(X.nnz)]
+        distinct = set(tuples)
+        for e, t in enumerate(tuples):
+            assert rows[e] == sum(1 for u in distinct if u < t)
+        ns = oracle.ttv_coords(X.subs, X.shape, mode)
+        if X.nnz:
+            assert np.array_equal(ns[rows], X.subs[:, R])
+            assert set(rows.tolist()) == set(range(ns.shape[0]))
+            _, inv = np.unique(X.subs[:, R], axis=0, return_inverse=True)
+            assert np.array_equal(rows, inv.reshape(-1))
+
+
+def test_rows_sum_to_ttv():
+    """Summing each nonzero's product into its row gives ttv's values (the
+    grouping the adjoint reuses)."""
+    rng = np.random.default_rng(77)
+    dims = (9, 5, 7, 4)
+    subs = np.column_stack([rng.integers(0, s, 3000) for s in dims])
+    vals = rng.integers(-9, 10, 3000).astype(np.float64)
+    for mode in range(4):
+        v = rng.integers(-5, 6, dims[mode]).astype(np.float64)
+        _, nv, _ = oracle.ttv(subs, vals, dims, mode, v)
+        rows = oracle.ttv_rows(subs, dims, mode)
+        acc = np.zeros(nv.shape[0])
+        np.add.at(acc, rows, vals * v[subs[:, mode]])  # integers: exact in any order
+        assert np.array_equal(acc, nv)
