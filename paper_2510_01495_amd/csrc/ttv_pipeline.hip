@@ -858,19 +858,35 @@ __device__ __forceinline__ void classify_item(WsView W, Ctrl* C, int level, int 
 // records keep their order (rounds of 2048; inside a round wave-major, then
 // item, then lane), so bucket contents are in input order.
 // ---------------------------------------------------------------------------
+// Jobs of few digits write each round through an LDS stage in destination
+// order: a round's records of one bucket leave as one run of consecutive
+// addresses instead of one scattered 16-byte store each.  The counters fit
+// jobs of up to kSortedDig digits; measured, the extra barriers and LDS
+// passes cost more than the runs save from 512 digits on (about 4 records
+// per bucket and round), so only jobs of at most kSortedRounds digits (8 or
+// more records per bucket and round) take them.
+constexpr int kSortedDig = 1024;
+constexpr int kSortedRounds = 256;
 template <typename IdxT, int MO>
 struct ScatterSmem {
-  unsigned cursor[kNDig];  // next position of every bucket
-  IdxT stage[kScatterThreads / 64][64 * MO];
+  // next position of every bucket; with at most kSortedDig digits the upper
+  // three quarters hold the round's digit counts, their exclusive scan and
+  // the position of round slot 0 per digit
+  unsigned cursor[kNDig];
+  union {
+    IdxT stage[kScatterThreads / 64][64 * MO];      // level-1 index rows (load_round)
+    u64x2 stg[kScatterThreads * kScatterIPT];       // a round's records by rank
+  };
   unsigned wsum[kScatterThreads / 64];
 };
+static_assert(4 * kSortedDig <= kNDig, "sorted rounds keep their counters in the cursor array");
 
 // The first `gc` blocks classify this level's buckets (classify_item over
 // njobs*slices items); the others scatter its tiles.  Neither role reads what
 // the other writes in this launch.
 template <typename IdxT, int F, int PM, int MO>
 __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(WsView W, int level, int T, int Tnext, int maxlevel,
-                                                             int slices, int gc) {
+                                                             int slices, int gc, int smax) {
   constexpr int IPT = kScatterIPT;
   constexpr int RW = 64 * IPT;            // records per wave per round
   constexpr int RN = kScatterThreads * IPT;
@@ -894,6 +910,10 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
   }
   ScatterSmem<IdxT, MO>& ss = smem.sc;
   unsigned* cursor = ss.cursor;
+  unsigned* const ls = cursor + kSortedDig;      // round: exclusive scan of the digit counts
+  unsigned* const ob = cursor + 2 * kSortedDig;  // round: cursor before the round minus ls
+  unsigned* const lc = cursor + 3 * kSortedDig;  // round: digit counts
+  u64x2* const stg = ss.stg;
   auto& stage = ss.stage;
   unsigned* wsum_s = ss.wsum;
   const int ntiles = clampi(C->ntiles[level], W.L.tcap);
@@ -969,13 +989,79 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
           for (int j = 0; j < IPT; ++j) ax[j] = (int32_t)(roff + i0 + j * 64);  // the nonzero's index in its tensor
         }
       }
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) dg[j] = (unsigned)(key[j] >> J.shift) & mask;
+      if (PM != kPipeTTVSeg && nd <= smax) {  // uniform over the block (smax <= kSortedDig)
+        // ranks within the round by (digit, input order): the waves take
+        // turns on the round's digit counters (lanes of one LDS atomic on
+        // one counter served in lane order), so each record's position is
+        // the one the direct path below gives it
+        for (int q = threadIdx.x; q < nd; q += kScatterThreads) lc[q] = 0u;
+        __syncthreads();
+        unsigned lpos[IPT];
+        for (int turn = 0; turn < kScatterThreads / 64; ++turn) {
+          if (w == turn) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+              const long long i = rb + (long long)w * RW + j * 64 + ln;
+              lpos[j] = i < n ? atomicAdd(&lc[dg[j]], 1u) : 0u;
+            }
+          }
+          __syncthreads();
+        }
+        {
+          constexpr int DPS = kSortedDig / kScatterThreads;
+          const int d0 = threadIdx.x * DPS;
+          unsigned v[DPS], sum = 0;
+#pragma unroll
+          for (int q = 0; q < DPS; ++q) {
+            v[q] = d0 + q < nd ? lc[d0 + q] : 0u;
+            sum += v[q];
+          }
+          unsigned all;
+          unsigned ex = block_excl_scan<kScatterThreads>(sum, wsum_s, all);
+#pragma unroll
+          for (int q = 0; q < DPS; ++q) {
+            if (d0 + q < nd) {
+              ls[d0 + q] = ex;
+              ob[d0 + q] = cursor[d0 + q] - ex;  // modulo 2^32: ob + rank is the position
+              cursor[d0 + q] += v[q];
+            }
+            ex += v[q];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const long long i = rb + (long long)w * RW + j * 64 + ln;
+          if (i < n) {
+            const unsigned rk = ls[dg[j]] + lpos[j];
+            if (rk < (unsigned)RN) {  // always, unless the counters are corrupt: then report, never write outside
+              u64x2 r;
+              r.x = key[j];
+              r.y = pay[j];
+              stg[rk] = r;
+            } else {
+              set_error(C, TTV_E_DEVICE);
+            }
+          }
+        }
+        __syncthreads();
+        // consecutive lanes take consecutive ranks: runs of one bucket go
+        // out as consecutive addresses
+        const int cnt = (int)((n - rb) < (long long)RN ? (n - rb) : (long long)RN);
+        for (int q = threadIdx.x; q < cnt; q += kScatterThreads) {
+          const u64x2 r = stg[q];
+          gdst[ob[(unsigned)(r.x >> J.shift) & mask] + (unsigned)q] = r;
+        }
+        __syncthreads();  // the stage and the round counters are reused by the next round
+        continue;
+      }
       // positions: the waves take turns adding to the bucket cursors; in a
       // wave, items in order, and the lanes of one LDS atomic that hit the
       // same cursor are served in lane order, so every bucket receives the
       // round's records in input order (wave, item, lane)
       unsigned pos[IPT];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) dg[j] = (unsigned)(key[j] >> J.shift) & mask;
       for (int turn = 0; turn < kScatterThreads / 64; ++turn) {
         if (w == turn) {
 #pragma unroll
@@ -1867,7 +1953,7 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     const int gc = std::min(gj * slices, 4 * cus);
     if (l == 1) prof_begin(TTV_PROF_SCATTER1, s);
     hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gc + gt), dim3(kScatterThreads), 0, s, W, l, T, Tn,
-                       P.levels, slices, gc);
+                       P.levels, slices, gc, kSortedRounds);
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);

@@ -397,3 +397,31 @@ def test_few_keys_integer_exact_and_validate():
     op = P.TTVOp(torch.from_numpy(bad).cuda(), vals, shape, [mode], [v], flags=L.VALIDATE)
     op.launch()
     assert op.device_error() == -8
+
+
+@pytest.mark.parametrize("nnz,shape", [(150_000, (300, 40, 500)), (40_000, (3000, 9, 2000))])
+def test_sorted_rounds_integer_exact(nnz, shape):
+    """First-level jobs of at most 256 digits write their rounds through the
+    LDS stage in destination order: integer values (exact in any order), so
+    coordinates and values equal the oracle's bit for bit; the segment map
+    and the permutation mode (plan reuse) take the same path."""
+    import torch
+    P = _api()
+    X = synth.tiny(170 + nnz % 97, 3, shape, nnz, value_dist="int_f64")
+    rng = np.random.default_rng(nnz)
+    v = rng.integers(-3, 4, shape[1]).astype(np.float64)
+    subs, vals, gv_ = to_gpu(X, v)
+    info = P.plan_query(subs, vals, X.shape, [1])
+    assert info.digit1_bits <= 8, info.digit1_bits
+    say(f"sorted rounds: nnz={nnz} digit bits {info.digit1_bits}")
+    gs, gv, _ = P.ttv(subs, vals, X.shape, 1, gv_)
+    ns, nv, _ = oracle.ttv(X.subs, X.vals, X.shape, 1, v)
+    assert np.array_equal(gs.cpu().numpy(), ns) and np.array_equal(gv.cpu().numpy(), nv)
+    g = rng.integers(-2, 3, ns.shape[0]).astype(np.float64)
+    grads, gvals = P.ttv_backward(subs, vals, X.shape, "sparse", 1, [None, gv_, None], torch.from_numpy(g).cuda())
+    wv, wvals = oracle.ttv_vjp(X.subs, X.vals, X.shape, 1, v, g)
+    assert np.array_equal(grads[1].cpu().numpy(), wv) and np.array_equal(gvals.cpu().numpy(), wvals)
+    R = P.ReuseTTV(subs, vals, X.shape, 1)
+    R.apply(gv_)
+    rs, rv, _ = R.result()
+    assert np.array_equal(rs.cpu().numpy(), ns) and np.array_equal(rv.cpu().numpy(), nv)
