@@ -34,7 +34,7 @@ constexpr int kFinishIPT = kCap / kFinishThreads;
 constexpr int kSortDigit = 8;            // LDS radix digit width
 constexpr int kDenseBits = 12;           // a bucket whose keys span at most this many bits is summed by key
                                          // in LDS (a dense leaf), whatever its size
-constexpr int kDenseTile = 32768;        // records of a dense leaf per block of partial sums (larger leaves)
+constexpr int kDenseTile = 16384;        // records of a dense leaf per block of partial sums (larger leaves)
 constexpr int kDenseSlotWords = (1 << kDenseBits) + (1 << kDenseBits) / 64;  // sums + presence bits
 
 // Value forms.

@@ -104,11 +104,31 @@ extern "C" int ttv_debug_phases2_reset() {
   unsigned long long z[16] = {0};
   return (int)hipMemcpyToSymbol(HIP_SYMBOL(g_phase2), z, sizeof(z));
 }
+// look-back statistics per leaf kind k (0 dense, 1 pure, 2 sort-free, 3
+// sorted): wall time at slot 5 + k, polling rounds at 9 + k; steps at 13,
+// look-backs at 14, look-backs that polled at 15
+#define TTV_LB_DECL                                 \
+  const unsigned long long lb_t0 = wall_clock64(); \
+  unsigned lb_steps = 0, lb_waits = 0;
+#define TTV_LB_STEP ++lb_steps;
+#define TTV_LB_WAIT ++lb_waits;
+#define TTV_LB_END(k)                                                  \
+  if (lane_id() == 0) {                                                \
+    atomicAdd(&g_phase2[5 + (k)], wall_clock64() - lb_t0);            \
+    atomicAdd(&g_phase2[9 + (k)], (unsigned long long)lb_waits);      \
+    atomicAdd(&g_phase2[13], (unsigned long long)lb_steps);           \
+    atomicAdd(&g_phase2[14], 1ull);                                    \
+    if (lb_waits) atomicAdd(&g_phase2[15], 1ull);                      \
+  }
 #else
 #define TTV_PHASE_DECL
 #define TTV_PHASE(i)
 #define TTV_COUNT(i)
 #define TTV_PHASE2(i)
+#define TTV_LB_DECL
+#define TTV_LB_STEP
+#define TTV_LB_WAIT
+#define TTV_LB_END(k)
 #endif
 
 constexpr unsigned long long kFlagAgg = 1ull << 62;
@@ -1270,7 +1290,7 @@ __device__ __forceinline__ void publish(unsigned long long* S, int r, unsigned l
 // meaning (an aggregate stays the leaf's count), so only the words still 0
 // are read again.
 __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit, Ctrl* C,
-                                   unsigned long long early = 0) {
+                                   unsigned long long early = 0, int kind = 0) {
   // Each step reads kLookG groups of 64 predecessors, their loads in flight
   // together (lane l of group g reads predecessor base - 64 g - l).  The
   // groups are then resolved nearest first: a lane waits only while its
@@ -1281,7 +1301,9 @@ __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit,
   constexpr int kLookG = 4;
   const unsigned ln = lane_id();
   long long prefix = 0;
+  TTV_LB_DECL
   for (int base = r - 1;; base -= 64 * kLookG) {
+    TTV_LB_STEP
     unsigned long long s[kLookG];
 #pragma unroll
     for (int g = 0; g < kLookG; ++g) {
@@ -1305,6 +1327,7 @@ __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit,
         stop = pm ? __ffsll((long long)pm) - 1 : 63;
         const bool need = (int)ln <= stop && j >= 0 && !(s[g] >> 62);
         if (!ballot(need)) break;
+        TTV_LB_WAIT
         if (need) {
           if (++spins > spin_limit) {
             set_error(C, TTV_E_DEVICE);
@@ -1326,6 +1349,8 @@ __device__ long long lookback_wave(unsigned long long* S, int r, int spin_limit,
     prefix += v;
     if (found) break;
   }
+  TTV_LB_END(kind)
+  (void)kind;
   return prefix;
 }
 
@@ -1401,6 +1426,15 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
   __shared__ int s_ticket;
   __shared__ long long s_prefix;
   __shared__ OutInfo<IdxT, F> sO;
+  // the tensor whose output layout sO holds, with its record range and
+  // output pointers (reloaded only when a leaf of another tensor comes)
+  struct TensorOut {
+    long long base, nnz;
+    long long* out_nnz;
+    int32_t* seg_out;
+    int tensor;
+  };
+  __shared__ TensorOut sT;
   Ctrl* C = W.ctrl();
   if (aborted(C)) return;
   const int nleaves = clampi(C->nleaves, W.L.lcap);
@@ -1408,6 +1442,10 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
   TTV_PHASE_DECL
+  // Tickets hand out the leaves in key order, each when a block is free to
+  // start it (a leaf ticketed ahead of time would hold up the look-backs of
+  // every later leaf until its block got to it).
+  if (tid == 0) sT.tensor = -1;
   for (;;) {
     if (tid == 0) s_ticket = atomicAdd(&C->ticket, 1);
     __syncthreads();
@@ -1416,12 +1454,19 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     TTV_PHASE(0)
     const Leaf Lf = W.ordered()[r];
     const TDesc& D = W.desc()[Lf.tensor];
-    const bool first = Lf.start == D.base;
-    const bool last = Lf.start + Lf.size == D.base + D.nnz;
-    gptr<long long> out_nnz = to_global(D.out_nnz);
-    gptr<int32_t> seg_out = to_global(D.seg_out);
-    if (tid == 0) sO.load(D);
+    if (tid == 0 && Lf.tensor != sT.tensor) {
+      sO.load(D);
+      sT.base = D.base;
+      sT.nnz = D.nnz;
+      sT.out_nnz = D.out_nnz;
+      sT.seg_out = D.seg_out;
+      sT.tensor = Lf.tensor;
+    }
     __syncthreads();
+    const bool first = Lf.start == sT.base;
+    const bool last = Lf.start + Lf.size == sT.base + sT.nnz;
+    gptr<long long> out_nnz = to_global(sT.out_nnz);
+    gptr<int32_t> seg_out = to_global(sT.seg_out);
     const OutInfo<IdxT, F>& O = sO;
     const gptr<const Rec> R = to_global(static_cast<const Rec*>(W.rec(Lf.src))) + Lf.start;
     const gptr<const u64x2> Rv = to_global(reinterpret_cast<const u64x2*>(W.rec(Lf.src))) + Lf.start;
@@ -1471,7 +1516,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         }
       }
       if (w == 0) {
-        const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
+        const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, 0ull, 0);
         if (ln == 0) {
           if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u));
           s_prefix = prefix;
@@ -1512,7 +1557,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     if (Lf.kind == kLeafPure) {
       if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | 1ull);
       if (w == 0) {
-        const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C);
+        const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, 0ull, 1);
         if (ln == 0) {
           if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + 1));
           s_prefix = prefix;
@@ -1667,7 +1712,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
           }
           TTV_PHASE2(2)
           if (w == 0) {
-            const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early);
+            const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early, 2);
             if (ln == 0) {
               if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u_early));
               s_prefix = prefix;
@@ -1821,7 +1866,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
     }
     // wave 0 resolves this leaf's output offset while the others gather payloads
     if (w == 0) {
-      const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early);
+      const long long prefix = first ? 0 : lookback_wave(S, r, spin_limit, C, lb_early, 3);
       if (ln == 0) {
         if (!first) publish(S, r, kFlagInc | (unsigned long long)(prefix + u));
         s_prefix = prefix;

@@ -1,7 +1,7 @@
 """GPU parity of the dense leaves: buckets larger than an LDS leaf whose keys
 span at most 12 bits are summed by key (Eq. 3 per output row) instead of
 being split again.  Skewed tensors put such buckets on every path: summed by
-one block (4096 < size <= 32768 records), by several blocks of partial sums
+one block (4096 < size <= 16384 records), by several blocks of partial sums
 combined in tile order (larger), and after a second bucket level (Zipf
 keys); FP64 and compensated FP32 forms, row- and column-major subs, the
 sparse adjoint's segment map, exact-zero removal and a batch.  Coordinates
@@ -24,7 +24,7 @@ def _skewed(seed, hot, cold, idx=np.int64, val="u01_f64"):
     bucket on uniform keys: r = 7 for 60K-120K nonzeros, 9 for 250K, 11 for
     1.2M-1.5M, 12 above 2M), so the hot keys fill 4000 / 2^(19-r) buckets of
     19 - r key bits: one dense leaf of `hot` records at r = 7 (summed by one
-    block up to 32768 records), several multi-block dense leaves above."""
+    block up to 16384 records), several multi-block dense leaves above."""
     rng = np.random.default_rng(seed)
     shape = (100, 50, 4000)
     h = np.column_stack([np.zeros(hot, np.int64), rng.integers(0, 50, hot), rng.integers(0, 4000, hot)])
@@ -37,7 +37,8 @@ def _skewed(seed, hot, cold, idx=np.int64, val="u01_f64"):
     return synth.COO(np.ascontiguousarray(subs), vals, shape)
 
 
-@pytest.mark.parametrize("hot,cold,soa", [(25_000, 60_000, False), (25_000, 60_000, True), (200_000, 50_000, False),
+@pytest.mark.parametrize("hot,cold,soa", [(12_000, 60_000, False), (25_000, 60_000, False), (25_000, 60_000, True),
+                                          (200_000, 50_000, False),
                                           (200_000, 50_000, True), (2_500_000, 50_000, False)])
 def test_dense_leaves_f64(hot, cold, soa):
     import paper_2510_01495_amd as P
@@ -57,7 +58,7 @@ def test_dense_leaves_f64(hot, cold, soa):
     check_ttv(X, 1, v, gs, gv, F64_TOL, "dense FP64")
 
 
-@pytest.mark.parametrize("hot,cold", [(20_000, 70_000), (150_000, 30_000), (1_500_000, 30_000)])
+@pytest.mark.parametrize("hot,cold", [(10_000, 70_000), (20_000, 70_000), (150_000, 30_000), (1_500_000, 30_000)])
 def test_dense_leaves_c32(hot, cold):
     import paper_2510_01495_amd as P
     X = _skewed(21, hot, cold, idx=np.int32, val="normal_f32")
