@@ -1492,11 +1492,15 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       }
       const long long slotw = dense_slot_words(Lf.bits);
       const gptr<const unsigned long long> slots = to_global((const unsigned long long*)W.dpool()) + Lf.pslot;
-      {
-        for (int q = tid; q < words; q += NT) {
-          unsigned m = 0u;
-          for (int t = 0; t < Lf.nptiles; ++t) m |= ((const gptr<const unsigned>)(slots + t * slotw + nk))[q];
-          pres[q] = m;
+      {  // every (tile, word) pair by its own thread: the loads are all in flight at once
+        for (int q = tid; q < words; q += NT) pres[q] = 0u;
+        __syncthreads();
+        const int wsh = Lf.bits > 5 ? Lf.bits - 5 : 0;  // words = 2^wsh
+        const int tot = Lf.nptiles << wsh;
+        for (int e = tid; e < tot; e += NT) {
+          const int t = e >> wsh, q = e & (words - 1);
+          const unsigned m = ((const gptr<const unsigned>)(slots + t * slotw + nk))[q];
+          if (m) atomicOr(&pres[q], m);
         }
         __syncthreads();
       }
@@ -1508,10 +1512,18 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         if (tid < words) wpre[tid] = ex;
       }
       if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);
-      if (pm_values(PM) && Lf.nptiles > 0) {  // the slots' sums, tile by tile
+      if (pm_values(PM) && Lf.nptiles > 0) {  // the slots' sums, tile by tile (8 loads in flight)
         for (int q = tid; q < nk; q += NT) {
           double a = 0.0;
-          for (int t = 0; t < Lf.nptiles; ++t) a += __longlong_as_double((long long)slots[t * slotw + q]);
+          int t = 0;
+          for (; t + 8 <= Lf.nptiles; t += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = __longlong_as_double((long long)slots[(t + u) * slotw + q]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += x[u];
+          }
+          for (; t < Lf.nptiles; ++t) a += __longlong_as_double((long long)slots[t * slotw + q]);
           sums[q] = a;
         }
       }
@@ -1739,6 +1751,44 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
         }
       }
     }
+    // Wider relative keys (up to 31 bits): the distinct keys are counted
+    // before the sort as well, by inserting them into an LDS hash set (twice
+    // as many slots as a leaf has records, linear probing), so such a leaf
+    // publishes its count as early as a bitmap-counted one and later leaves
+    // do not wait for its sort in their look-backs.
+    const bool hashed = !wide && !early && Lf.bits <= 31;
+    if (hashed) {
+      constexpr int kSlotBits = 13;
+      constexpr int kSlots = 1 << kSlotBits;
+      constexpr unsigned kEmpty = 0xffffffffu;  // no key of at most 31 bits
+      static_assert(kSlots >= 2 * kCap && kSlots * 4 <= (int)sizeof(smA), "hash set of the leaf's keys in region A");
+      unsigned* const tab = reinterpret_cast<unsigned*>(smA);
+      for (int q = tid; q < kSlots; q += NT) tab[q] = kEmpty;
+      __syncthreads();
+      unsigned mine = 0;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const int i = w * 64 * nj + j * 64 + (int)ln;
+        if (j < nj && i < n) {
+          unsigned h = (k[j] * 2654435761u) >> (32 - kSlotBits);
+          for (int probe = 0; probe < kSlots; ++probe) {  // the set never fills: it ends at an empty slot
+            const unsigned old = atomicCAS(&tab[h], kEmpty, k[j]);
+            if (old == kEmpty) {
+              ++mine;
+              break;
+            }
+            if (old == k[j]) break;
+            h = (h + 1) & (unsigned)(kSlots - 1);
+          }
+        }
+      }
+      block_excl_scan<NT>(mine, wsum, u_early);  // its barriers end the set's use before the sort reuses region A
+      if (tid == 0) publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u_early);
+      if (w == 0 && !first) {
+        const int jp = r - 1 - (int)ln;
+        lb_early = jp >= 0 ? __hip_atomic_load(&S[jp], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kFlagInc;
+      }
+    }
     const int npass = (Lf.bits + MAXD - 1) / MAXD;
     const int dw = npass ? (Lf.bits + npass - 1) / npass : 0;
     const int nb = 1 << dw;
@@ -1859,7 +1909,7 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
       hbw += (q < w) ? c : 0u;
       u += c;
     }
-    if (early) {
+    if (early || hashed) {
       if (tid == 0 && u != u_early) set_error(C, TTV_E_DEVICE);  // the two counts agree by construction
     } else if (tid == 0) {
       publish(S, r, (first ? kFlagInc : kFlagAgg) | (unsigned long long)u);

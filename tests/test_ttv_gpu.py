@@ -425,3 +425,38 @@ def test_sorted_rounds_integer_exact(nnz, shape):
     R.apply(gv_)
     rs, rv, _ = R.result()
     assert np.array_equal(rs.cpu().numpy(), ns) and np.array_equal(rv.cpu().numpy(), nv)
+
+
+@pytest.mark.parametrize("dups", [1, 3, 40])
+def test_wide_leaves_counted_before_the_sort(dups):
+    """Leaves of 17-31 key bits count their distinct keys in an LDS hash set
+    before sorting (the sort then checks the count): 30-bit keys, first digit
+    of 7 bits, each distinct tuple repeated about `dups` times; integer values
+    (exact in any order), every pipeline mode that sorts such leaves."""
+    import torch
+    P = _api()
+    rng = np.random.default_rng(300 + dups)
+    shape = (20000, 7, 30000)
+    n = 120_000
+    base = np.column_stack([rng.integers(0, shape[0], n // dups + 1), rng.integers(0, shape[2], n // dups + 1)])
+    pick = rng.integers(0, base.shape[0], n)
+    subs = np.column_stack([base[pick, 0], rng.integers(0, shape[1], n), base[pick, 1]]).astype(np.int64)
+    X = synth.COO(subs, rng.integers(-5, 6, n).astype(np.float64), shape)
+    v = rng.integers(-3, 4, shape[1]).astype(np.float64)
+    subs_g, vals_g, gv_ = to_gpu(X, v)
+    info = P.plan_query(subs_g, vals_g, X.shape, [1])
+    assert 16 < info.key_bits - info.digit1_bits <= 31, (info.key_bits, info.digit1_bits)
+    ns, nv, _ = oracle.ttv(X.subs, X.vals, X.shape, 1, v)
+    gs, gv, _ = P.ttv(subs_g, vals_g, X.shape, 1, gv_)
+    assert np.array_equal(gs.cpu().numpy(), ns) and np.array_equal(gv.cpu().numpy(), nv)
+    ss, sv, _, seg = P.ttv_save(subs_g, vals_g, X.shape, 1, gv_)
+    assert np.array_equal(ss.cpu().numpy(), ns) and np.array_equal(sv.cpu().numpy(), nv)
+    assert np.array_equal(seg.cpu().numpy().astype(np.int64), oracle.ttv_rows(X.subs, X.shape, 1))
+    g = rng.integers(-2, 3, ns.shape[0]).astype(np.float64)
+    grads, gvals = P.ttv_backward(subs_g, vals_g, X.shape, "sparse", 1, [None, gv_, None], torch.from_numpy(g).cuda())
+    wv, wvals = oracle.ttv_vjp(X.subs, X.vals, X.shape, 1, v, g)
+    assert np.array_equal(grads[1].cpu().numpy(), wv) and np.array_equal(gvals.cpu().numpy(), wvals)
+    R = P.ReuseTTV(subs_g, vals_g, X.shape, 1)
+    R.apply(gv_)
+    rs, rv, _ = R.result()
+    assert np.array_equal(rs.cpu().numpy(), ns) and np.array_equal(rv.cpu().numpy(), nv)
