@@ -80,6 +80,19 @@ enum {
   TTV_E_ARG = -12       /* any other invalid argument */
 };
 
+/* Environment switches, read on every call:
+ *   TTV_LOG=1         every plan is printed to stderr (what runs, its sizes,
+ *                     digit widths, levels and workspace bytes).
+ *   TTV_FAULT=launch  every entry point that launches kernels returns
+ *                     TTV_E_HIP (ttv_last_hip_error: hipErrorLaunchFailure)
+ *                     once its arguments are validated, touching no device
+ *                     memory: a simulated launch failure for callers' tests.
+ *   TTV_FAULT=spin    the sorting pipeline's bounded waits give up at their
+ *                     first poll: a product whose leaves wait reports
+ *                     TTV_E_DEVICE (its output is then undefined, every write
+ *                     stays inside the caller's buffers).
+ * TTV_FAULT takes a comma-separated list of these names. */
+
 /* Flags. */
 #define TTV_VALIDATE 0x1 /* check every index on the device (async, see ttv_check_device_error) */
 #define TTV_OUT_F64 0x2  /* FP32 inputs: write FP64 result values instead of FP32 */

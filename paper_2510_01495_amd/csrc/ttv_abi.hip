@@ -2,6 +2,9 @@
 // dispatch of the sparse TTV pipeline (Eq. 3, Sec. 3.3).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
@@ -31,6 +34,31 @@ void prof_end(int kernel, hipStream_t s) {
   if (g_prof.kernel != kernel || g_prof.count >= (int)g_prof.stops.size()) return;
   hipEventRecord(static_cast<hipEvent_t>(g_prof.stops[g_prof.count]), s);
   ++g_prof.count;
+}
+
+bool log_on() {
+  const char* e = std::getenv("TTV_LOG");
+  return e && e[0] && std::strcmp(e, "0") != 0;
+}
+
+bool fault_on(const char* what) {
+  const char* e = std::getenv("TTV_FAULT");
+  if (!e) return false;
+  const size_t n = std::strlen(what);
+  for (const char* p = e; *p;) {
+    const char* q = std::strchr(p, ',');
+    const size_t len = q ? (size_t)(q - p) : std::strlen(p);
+    if (len == n && std::strncmp(p, what, n) == 0) return true;
+    if (!q) break;
+    p = q + 1;
+  }
+  return false;
+}
+
+int fault_launch() {
+  if (!fault_on("launch")) return TTV_OK;
+  set_last_hip_error((int)hipErrorLaunchFailure);
+  return TTV_E_HIP;
 }
 
 int device_cus() {
@@ -235,6 +263,12 @@ int finish_plan(PipePlan& P) {
   P.tiles1 = (P.total + P.T1 - 1) / P.T1;
   P.L = make_layout(P.total, 1, P.levels, P.T1, P.T2, P.tiles1, dense_bits_of(P.pipe_mode) > 0,
                     P.pipe_mode == kPipeTTVSeg);
+  if (log_on())
+    std::fprintf(stderr,
+                 "ttv: plan mode=%d form=%s index=%s nnz=%lld order=%d kept=%d key_bits=%d digit1=%d levels=%d "
+                 "tile1=%d tile=%d workspace=%zu\n",
+                 P.pipe_mode, P.form == kF64 ? "f64" : "c32", P.idx64 ? "i64" : "i32", (long long)P.total,
+                 (int)P.d0.order, (int)P.d0.nrem, (int)P.d0.keybits, (int)P.d0.r1, P.levels, P.T1, P.T2, P.L.end);
   return TTV_OK;
 }
 
@@ -338,6 +372,7 @@ int ttv_coo_multi(const ttv_coo_desc* X, int32_t ncon, const int32_t* modes, con
   size_t need = drop ? tmp_off + drop_zeros_ws(X->nnz, P.d0.nrem, P.idx64, of64) : P.L.end;
   if (keyed_fits(P, flags)) need = std::max(need, keyed_ws(P));
   if (!ws || ws_bytes < need) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   P.cus = device_cus();
   if (!drop) {
@@ -394,6 +429,7 @@ int ttv_coo_save(const ttv_coo_desc* X, int32_t mode, const void* v, int64_t v_l
   if (v_len != X->shape[mode]) return TTV_E_SHAPE;
   if (X->nnz > 0 && (!v || !out_subs || !out_vals || !seg)) return TTV_E_NULL;
   if (!ws || ws_bytes < P.L.end) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   P.d0.vec[mode] = v;
   P.d0.out_subs = out_subs;

@@ -8,6 +8,8 @@
 // output.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
@@ -169,6 +171,9 @@ int run_pass(const Pass& p, DenseArgs A, char* ws, size_t part_off, void* const*
   A.err = reinterpret_cast<int32_t*>(ws + offsetof(Ctrl, error));
   A.out_f64 = out_f64;
   const size_t lds = A.acc_bytes + p.tile;
+  if (log_on())
+    std::fprintf(stderr, "ttv: dense pass accumulators=%d entries=%lld grad_vals=%d grid=%d lds=%zu nnz=%lld\n",
+                 p.nacc, (long long)off, A.grad_vals ? 1 : 0, p.grid, lds, (long long)A.nnz);
   return launch_dense(A, idx64, form, p.grid, lds, s);
 }
 
@@ -359,6 +364,7 @@ int ttv_coo_allbut(const ttv_coo_desc* X, int32_t keep, const void* const* vecs,
   plan_passes(X, &keep, 1, false, passes, npass, fb, nfb);
   const DenseWs W = layout_dense(X, flags, passes, npass, fb, nfb, 0, false);
   if (!ws || ws_bytes < W.total) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
@@ -402,6 +408,7 @@ int ttv_coo_allbut_noalloc(const ttv_coo_desc* X, int32_t keep, const void* cons
   if (nfb) return TTV_E_SIZE;  // the kept mode's accumulator does not fit in LDS: needs the sorting pipeline
   const DenseWs W = layout_dense(X, flags, passes, npass, fb, nfb, 0, false);
   if (W.total > kNoAllocScratch) return TTV_E_SIZE;
+  if (int f = fault_launch()) return f;
   void* ws = nullptr;
   rc = scratch_address(&ws);
   if (rc) return rc;
@@ -459,6 +466,7 @@ int ttv_coo_backward(const ttv_coo_desc* X, int32_t kind, int32_t mode_or_keep, 
   if (rc) return rc;
   if (!vecs || !vec_lens || !grad_vecs) return TTV_E_NULL;
   if (!grad_out && X->nnz > 0) return TTV_E_NULL;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
@@ -575,6 +583,7 @@ int ttv_coo_backward_saved(const ttv_coo_desc* X, int32_t mode, const void* cons
   plan_passes(X, modes, grad_vecs[mode] ? 1 : 0, grad_vals != nullptr, passes, npass, fb, nfb);
   for (int p = 0; p < npass; ++p)
     if (W.part_off + pass_ws(passes[p]) > W.total) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   const int out_f64 = form == kF64 ? 1 : 0;

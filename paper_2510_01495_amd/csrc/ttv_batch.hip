@@ -69,6 +69,9 @@ void apply_tuning(ttv_batch_plan* p, const Tuning& t) {
   P.levels = levels;
   P.tiles1 = tiles1;
   P.L = make_layout(P.total, P.count, P.levels, P.T1, P.T2, tiles1, true);
+  if (log_on())
+    std::fprintf(stderr, "ttv: batch plan tensors=%d records=%lld levels=%d tile1=%d digit1_bias=%d workspace=%zu\n",
+                 P.count, (long long)P.total, P.levels, P.T1, t.r1_bias, P.L.end);
   p->tuning = t;
   if (p->descs_dev)  // the device copy follows the tuning (never while a call may run)
     hipMemcpy(p->descs_dev, P.descs.data(), sizeof(TDesc) * (size_t)P.count, hipMemcpyHostToDevice);
@@ -247,12 +250,14 @@ int ttv_batch_workspace(const ttv_batch_plan* plan, size_t* bytes) {
 int ttv_coo_batched(const ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_stream_t stream) {
   if (!plan) return TTV_E_NULL;
   if (!ws || ws_bytes < plan->P.L.end) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   return launch_pipeline(plan->P, ws, reinterpret_cast<hipStream_t>(stream));
 }
 
 int ttv_batch_autotune(ttv_batch_plan* plan, void* ws, size_t ws_bytes, ttv_stream_t stream) {
   if (!plan) return TTV_E_NULL;
   if (!ws || ws_bytes < plan->ws_max) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TTV_E_HIP;

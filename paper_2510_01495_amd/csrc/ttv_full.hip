@@ -235,6 +235,7 @@ int ttv_coo_full(const ttv_coo_desc* X, const void* const* vecs, const int64_t* 
     if (!vecs[j] && X->nnz > 0) return TTV_E_NULL;
   }
   if (!ws || ws_bytes < kFullHdr + sizeof(double) * (size_t)kFullWaves) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   char* w = static_cast<char*>(ws);

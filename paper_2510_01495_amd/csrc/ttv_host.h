@@ -30,6 +30,19 @@ struct PipePlan {
 
 void set_last_hip_error(int e);
 int device_cus();
+// Environment switches, read on every call.
+//   TTV_LOG=1          the planners print each plan to stderr (what runs, its
+//                      sizes and workspace).
+//   TTV_FAULT=launch   every entry point that would launch kernels returns
+//                      TTV_E_HIP (hipErrorLaunchFailure) after validating its
+//                      arguments, without touching the device.
+//   TTV_FAULT=spin     the bounded waits of the sorting pipeline give up at
+//                      once (TTV_E_DEVICE from the device error word); every
+//                      kernel still ends and writes only inside its buffers.
+// TTV_FAULT takes a comma-separated list of these names.
+bool log_on();
+bool fault_on(const char* what);
+int fault_launch();  // TTV_E_HIP if TTV_FAULT names "launch", else TTV_OK
 int launch_pipeline(const PipePlan& P, void* ws, hipStream_t s);
 int plan_tensor(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, TDesc& D, int& form, int& idx64);
 int plan_single(const ttv_coo_desc* X, int ncon, const int32_t* modes, int flags, int pipe_mode, PipePlan& P);

@@ -499,6 +499,7 @@ int ttv_mttkrp_setup(ttv_mttkrp_plan* plan, void* data, size_t data_bytes, void*
                      ttv_stream_t stream) {
   if (int rc = check_plan(plan)) return rc;
   if (!data || data_bytes < plan->data_bytes || !ws || ws_bytes < plan->setup_bytes) return TTV_E_WORKSPACE;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   char* d = static_cast<char*>(data);
@@ -580,6 +581,7 @@ int ttv_mttkrp_apply(const ttv_mttkrp_plan* plan, const void* const* factors, vo
   if (!factors || !M) return TTV_E_NULL;
   for (int f = 0; f < plan->nf; ++f)
     if (!factors[plan->others[f]] && plan->nnz > 0) return TTV_E_NULL;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   const int cus = device_cus();

@@ -212,6 +212,7 @@ int ttv_result_densify(int32_t order, const int64_t* shape, int32_t index_dtype,
     if (cells > ((unsigned __int128)1 << 62)) cells = (unsigned __int128)1 << 62;  // never dense
   }
   D.cells = (long long)cells;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   const int cus = device_cus();

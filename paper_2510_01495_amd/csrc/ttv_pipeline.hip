@@ -2055,7 +2055,8 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL((k_leaves<F, PM>), dim3(4 * cus), dim3(kLeavesThreads), 0, s, W);
   prof_begin(TTV_PROF_FINISH, s);
   // three blocks per CU: the finish needs about 49 KB of LDS per block
-  hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(3 * cus), dim3(kFinishThreads), 0, s, W, P.spin_limit);
+  hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(3 * cus), dim3(kFinishThreads), 0, s, W,
+                     fault_on("spin") ? 0 : P.spin_limit);
   prof_end(TTV_PROF_FINISH, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {

@@ -337,6 +337,7 @@ int ttv_reuse_setup(ttv_reuse_plan* plan, void* data, size_t data_bytes, void* o
   if (!out_nnz) return TTV_E_NULL;
   if (!data || data_bytes < plan->data_bytes || !ws || ws_bytes < plan->setup_bytes) return TTV_E_WORKSPACE;
   if (plan->nnz > 0 && !out_subs) return TTV_E_NULL;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();  // errors left by earlier, unrelated runtime calls are not ours
   char* d = static_cast<char*>(data);
@@ -406,6 +407,7 @@ int ttv_reuse_apply(const ttv_reuse_plan* plan, const void* v, int64_t v_len, vo
   if (v_len != plan->X.shape[plan->mode]) return TTV_E_SHAPE;
   if (plan->nnz == 0) return TTV_OK;
   if (!v || !out_vals) return TTV_E_NULL;
+  if (int f = fault_launch()) return f;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   (void)hipGetLastError();
   char* d = static_cast<char*>(plan->data);

@@ -236,3 +236,46 @@ def test_mttkrp_plan_host_checks():
     finally:
         lib.ttv_mttkrp_plan_destroy(plan)
     lib.ttv_mttkrp_plan_destroy(None)
+
+
+def test_plan_log(monkeypatch, capfd):
+    """TTV_LOG=1: the planner prints each plan (sizes, digit, levels,
+    workspace) to stderr; unset, it prints nothing."""
+    monkeypatch.delenv("TTV_LOG", raising=False)
+    rc, _ = _query(_desc((100, 80, 60), 10_000), [2])
+    assert rc == 0 and "ttv: plan" not in capfd.readouterr().err
+    monkeypatch.setenv("TTV_LOG", "1")
+    rc, info = _query(_desc((2000,) * 4, 50_000_000), [1])
+    err = capfd.readouterr().err
+    assert rc == 0 and "ttv: plan" in err
+    assert "nnz=50000000" in err and "key_bits=33" in err and f"levels={info.levels}" in err
+    assert f"workspace={info.workspace_bytes}" in err
+
+
+def test_fault_launch_returns_hip_error_before_the_device(monkeypatch):
+    """TTV_FAULT=launch: the entry points validate their arguments, then
+    report a launch failure (TTV_E_HIP, hipErrorLaunchFailure) without
+    touching the device (the pointers here are never dereferenced); argument
+    errors still come first.  Runs without a GPU."""
+    L, lib = _lib()
+    monkeypatch.setenv("TTV_FAULT", "spin,launch")
+    d = _desc((100, 80, 60), 10_000)
+    dummy = ctypes.c_void_p(4096)
+    nnz = ctypes.c_void_p(8192)
+    big = ctypes.c_size_t(1 << 40)
+    rc = lib.ttv_coo(ctypes.byref(d), 2, dummy, 60, dummy, dummy, nnz, dummy, big, 0, None)
+    assert rc == -9  # TTV_E_HIP
+    assert lib.ttv_last_hip_error() == 719  # hipErrorLaunchFailure
+    # an argument error is still reported as such
+    assert lib.ttv_coo(ctypes.byref(d), 2, dummy, 61, dummy, dummy, nnz, dummy, big, 0, None) == -4
+    vecs = (ctypes.c_void_p * 3)(4096, 4096, 4096)
+    lens = (ctypes.c_int64 * 3)(100, 80, 60)
+    assert lib.ttv_coo_allbut(ctypes.byref(d), 0, vecs, lens, dummy, dummy, big, 0, None) == -9
+    assert lib.ttv_coo_allbut_noalloc(ctypes.byref(d), 0, vecs, lens, dummy, 0, None) == -9
+    assert lib.ttv_coo_full(ctypes.byref(d), vecs, lens, dummy, dummy, big, 0, None) == -9
+    gv = (ctypes.c_void_p * 3)(None, None, 4096)
+    assert lib.ttv_coo_backward(ctypes.byref(d), 1, 0, vecs, lens, dummy, gv, dummy, dummy, big, 0, None) == -9
+    assert lib.ttv_coo_save(ctypes.byref(d), 2, dummy, 60, dummy, dummy, nnz, dummy, dummy, big, 0, None) == -9
+    gv2 = (ctypes.c_void_p * 3)(None, None, 4096)
+    assert lib.ttv_coo_backward_saved(ctypes.byref(d), 2, vecs, lens, dummy, dummy, gv2, dummy, dummy, big, 0,
+                                      None) == -9

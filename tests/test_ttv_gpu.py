@@ -460,3 +460,25 @@ def test_wide_leaves_counted_before_the_sort(dups):
     R.apply(gv_)
     rs, rv, _ = R.result()
     assert np.array_equal(rs.cpu().numpy(), ns) and np.array_equal(rv.cpu().numpy(), nv)
+
+
+def test_fault_spin_reports_device_error_and_recovers(monkeypatch):
+    """TTV_FAULT=spin: the finish's bounded look-back waits give up at their
+    first poll, so a product whose leaves wait reports TTV_E_DEVICE (every
+    kernel still ends, writing inside its buffers); without the switch the
+    same workspace gives the right result again."""
+    P = _api()
+    X, mode, v = synth.workload_zipf(scale=0.02)
+    subs, vals, gv_ = to_gpu(X, v)
+    op = P.TTVOp(subs, vals, X.shape, [mode], [gv_], out_f64=True)
+    monkeypatch.setenv("TTV_FAULT", "spin")
+    errs = []
+    for _ in range(3):  # a look-back that never has to wait does not trip it: try a few launches
+        op.launch()
+        errs.append(op.device_error())
+    say(f"device errors under TTV_FAULT=spin: {errs}")
+    assert -11 in errs  # TTV_E_DEVICE
+    monkeypatch.delenv("TTV_FAULT")
+    op.launch()
+    gs, gv, _ = op.result()
+    check_ttv(X, mode, v, gs, gv, C32_TOL, "after the fault")
