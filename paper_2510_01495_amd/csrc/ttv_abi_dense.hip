@@ -170,11 +170,33 @@ int run_pass(const Pass& p, DenseArgs A, char* ws, size_t part_off, void* const*
   A.partials = reinterpret_cast<double*>(ws + part_off);
   A.err = reinterpret_cast<int32_t*>(ws + offsetof(Ctrl, error));
   A.out_f64 = out_f64;
-  const size_t lds = A.acc_bytes + p.tile;
+  // factor vectors staged in LDS (mode order) while the block's LDS stays
+  // within the budget; the grid follows the blocks per CU that fit (never
+  // more than the pass was sized for)
+  size_t lds = A.acc_bytes + p.tile;
+  A.vst_at = lds;
+  const size_t esz = form == kF64 ? 8 : 4;
+  long long vo = 0;
+  for (int m = 0; m < kMaxOrder; ++m) {
+    A.vst_off[m] = -1;
+    if (m >= A.order || !A.fac[m]) continue;
+    const size_t bytes = align16((size_t)A.dims[m] * esz);
+    if (lds + bytes > kLdsBudget) continue;
+    A.vst_off[m] = vo;
+    vo += (long long)(bytes / esz);
+    lds += bytes;
+  }
+  int grid = p.grid;
+  if (lds > A.acc_bytes + p.tile) {
+    const int bpc = (int)std::max<size_t>(
+        1, std::min<size_t>(kMaxWavesPerCU / (kDenseThreads / 64), kLdsPerCU / std::max<size_t>(lds, 1)));
+    grid = std::min(grid, kAssumedCUs * bpc);
+  }
   if (log_on())
-    std::fprintf(stderr, "ttv: dense pass accumulators=%d entries=%lld grad_vals=%d grid=%d lds=%zu nnz=%lld\n",
-                 p.nacc, (long long)off, A.grad_vals ? 1 : 0, p.grid, lds, (long long)A.nnz);
-  return launch_dense(A, idx64, form, p.grid, lds, s);
+    std::fprintf(stderr,
+                 "ttv: dense pass accumulators=%d entries=%lld grad_vals=%d grid=%d lds=%zu staged=%lld nnz=%lld\n",
+                 p.nacc, (long long)off, A.grad_vals ? 1 : 0, grid, lds, vo, (long long)A.nnz);
+  return launch_dense(A, idx64, form, grid, lds, s);
 }
 
 int run_fallback(const ttv_coo_desc* X, int m, int flags, const void* const* fac, const void* segfac,

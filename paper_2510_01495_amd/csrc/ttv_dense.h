@@ -35,6 +35,8 @@ struct DenseArgs {
   long long acc_off[kDenseMaxAcc];  // entry offsets of the accumulators
   long long acc_total;              // sum of the accumulator lengths
   size_t acc_bytes;                 // LDS bytes of the accumulators (16-byte aligned)
+  size_t vst_at;                    // LDS byte offset of the staged factor vectors
+  long long vst_off[kMaxOrder];     // per mode: element offset of its staged vector, or -1 (gathered from HBM)
   int out_f64;
 };
 

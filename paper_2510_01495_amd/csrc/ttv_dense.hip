@@ -38,12 +38,22 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
   using FO = FormOps<F>;
   using In = typename FO::In;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // layout: FP64 accumulators | row stage IdxT[NW][64*MO]
+  // layout: FP64 accumulators | row stage IdxT[NW][64*MO] | staged factor vectors
   double* accs = reinterpret_cast<double*>(smem);
   IdxT* stage = reinterpret_cast<IdxT*>(smem + A.acc_bytes);
+  In* vst = reinterpret_cast<In*>(smem + A.vst_at);
   const int tid = threadIdx.x, w = tid >> 6;
   const unsigned ln = lane_id();
   for (int i = tid; i < A.acc_total; i += NT) accs[i] = 0.0;
+  // factor vectors that fit beside the accumulators are copied in once: their
+  // random per-nonzero gathers then read LDS instead of L2
+#pragma unroll
+  for (int m = 0; m < MO; ++m) {
+    if (m < A.order && A.vst_off[m] >= 0) {
+      const gptr<const In> src = to_global(static_cast<const In*>(A.fac[m]));
+      for (long long i = tid; i < A.dims[m]; i += NT) vst[A.vst_off[m] + i] = src[i];
+    }
+  }
   __syncthreads();
   const gptr<const In> vals = to_global(static_cast<const In*>(A.vals));
   const bool rowmajor = rows_coalesced(A.order, A.se, A.sj[1]);
@@ -93,8 +103,14 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
       for (int m = 0; m < MO; ++m) {
         const In* fac = m < A.order ? static_cast<const In*>(A.fac[m]) : nullptr;
         const gptr<const In> f = to_global(fac);
+        const long long so = m < A.order ? A.vst_off[m] : -1;  // uniform over the launch
+        if (fac && so >= 0) {
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) g[m][j] = (fac && s0 + j * 64 + (int)ln < n) ? f[x[m][j]] : (In)1;
+          for (int j = 0; j < IPT; ++j) g[m][j] = s0 + j * 64 + (int)ln < n ? vst[so + x[m][j]] : (In)1;
+        } else {
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) g[m][j] = (fac && s0 + j * 64 + (int)ln < n) ? f[x[m][j]] : (In)1;
+        }
       }
 #pragma unroll
       for (int m = 0; m < MO; ++m) {
