@@ -1184,7 +1184,22 @@ __device__ __forceinline__ void dense_tile(WsView W, const Leaf& Lf, int p, doub
   const long long e = (Lf.size - b < (long long)kDenseTile) ? Lf.size : b + kDenseTile;
   const gptr<const u64x2> R = to_global(reinterpret_cast<const u64x2*>(W.rec(Lf.src))) + Lf.start;
   const unsigned kmask = (unsigned)nk - 1u;
+  // the next round's records are loaded while this round is added (no global
+  // store is pending, so the turns' barriers do not wait for those loads)
+  u64x2 nx[kLeavesIPT];
+  auto fetch = [&](long long rb) {
+#pragma unroll
+    for (int j = 0; j < kLeavesIPT; ++j) {
+      const long long i = rb + (long long)w * 64 * kLeavesIPT + j * 64 + ln;
+      if (i < e) nx[j] = R[i];
+    }
+  };
+  fetch(b);
   for (long long rb = b; rb < e; rb += RN) {
+    u64x2 cur[kLeavesIPT];
+#pragma unroll
+    for (int j = 0; j < kLeavesIPT; ++j) cur[j] = nx[j];
+    if (rb + RN < e) fetch(rb + RN);
     unsigned k[kLeavesIPT];
     double v[kLeavesIPT];
 #pragma unroll
@@ -1193,7 +1208,7 @@ __device__ __forceinline__ void dense_tile(WsView W, const Leaf& Lf, int p, doub
       k[j] = 0xffffffffu;
       v[j] = 0.0;
       if (i < e) {
-        const u64x2 rc = R[i];
+        const u64x2 rc = cur[j];
         k[j] = (unsigned)(rc.x - Lf.base) & kmask;
         if (pm_values(PM)) v[j] = FO::to_f64(FO::from_pay(rc.y));
         atomicOr(&pres[k[j] >> 5], 1u << (k[j] & 31u));
