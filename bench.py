@@ -51,7 +51,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 REPS = 30
-ONLY = ("zipf_fp64", "zipf_fp32", "uniform", "allbut", "batch", "grad_fwd", "grad_bwd")
+ONLY = ("zipf_fp64", "zipf_fp32", "uniform", "allbut", "batch", "grad_fwd", "grad_bwd", "sweep1200")
 
 
 def log(*a):
@@ -540,6 +540,10 @@ def only_run(name, K, W):
         op = (P.TTVOp(subs, vals, X.shape, [0], [gv[0]]) if name == "uniform"
               else P.AllButOp(subs, vals, X.shape, 0, [None, gv[1], gv[2]]))
         fn = op.launch
+    elif name == "sweep1200":
+        W_, mw, vw = synth.workload_paper_sweep(1200)
+        fn = P.TTVOp(torch.from_numpy(W_.subs).cuda(), torch.from_numpy(W_.vals).cuda(), W_.shape, [mw],
+                     [torch.from_numpy(vw).cuda()]).launch
     elif name == "batch":
         # with TTV_TUNE_CACHE naming an existing autotuner cache the plan takes
         # its tuning from there (no tuning launches to profile)
