@@ -56,7 +56,28 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
   }
   __syncthreads();
   const gptr<const In> vals = to_global(static_cast<const In*>(A.vals));
+  // Row-major indices and the values of the block's next tile are loaded
+  // during the current tile's turns: after the current tile's gathers (the
+  // memory counter retires in issue order, so loads issued before them would
+  // hold them up) and before the adds, which wait only for LDS.  Only with
+  // one accumulator: the adjoints' several accumulators leave no registers
+  // for it (measured slower).
   const bool rowmajor = rows_coalesced(A.order, A.se, A.sj[1]);
+  const bool pre = NACC == 1 && rowmajor;
+  const int s0 = w * 64 * IPT;  // this wave's slice of a tile
+  IdxT rawn[IPT][MO];
+  In an[IPT];
+  auto issue = [&](long long t) {
+    const long long e0 = t * TA;
+    const int n = (int)((A.nnz - e0 < (long long)TA) ? A.nnz - e0 : (long long)TA);
+    rows_issue<IdxT, IPT, MO>(static_cast<const IdxT*>(A.subs), A.se, A.order, e0 + s0, (long long)n - s0, rawn);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int i = s0 + j * 64 + (int)ln;
+      an[j] = i < n ? vals[e0 + i] : (In)0;
+    }
+  };
+  if (pre && blockIdx.x < A.ntiles) issue(blockIdx.x);
   for (long long t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
     const long long e0 = t * TA;
     const int n = (int)((A.nnz - e0 < (long long)TA) ? A.nnz - e0 : (long long)TA);
@@ -67,11 +88,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
       uint64_t full[IPT];  // product of all factors (gradient w.r.t. vals)
       uint64_t pa[NACC][IPT];
       In a[IPT];
-      const int s0 = w * 64 * IPT;  // this wave's slice of the tile
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
         const int i = s0 + j * 64 + (int)ln;
-        a[j] = i < n ? vals[e0 + i] : (In)0;
+        a[j] = pre ? an[j] : (i < n ? vals[e0 + i] : (In)0);
         full[j] = FO::start_prod((In)1);
 #pragma unroll
         for (int q = 0; q < NACC; ++q) {
@@ -84,9 +104,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
       for (int m = 0; m < MO; ++m)
 #pragma unroll
         for (int j = 0; j < IPT; ++j) x[m][j] = 0;
-      for_rows<IdxT, IPT, MO>(static_cast<const IdxT*>(A.subs), A.se, A.sj[1], A.order, rowmajor, e0 + s0,
-                              (long long)n - s0, stage + (size_t)w * 64 * MO,
-                              [&](int m, int j, long long v) { x[m][j] = v; });
+      if (pre)
+        rows_deliver<IdxT, IPT, MO>(rawn, A.se, A.order, stage + (size_t)w * 64 * MO,
+                                    [&](int m, int j, long long v) { x[m][j] = v; });
+      else
+        for_rows<IdxT, IPT, MO>(static_cast<const IdxT*>(A.subs), A.se, A.sj[1], A.order, rowmajor, e0 + s0,
+                                (long long)n - s0, stage + (size_t)w * 64 * MO,
+                                [&](int m, int j, long long v) { x[m][j] = v; });
       if (A.validate) {
 #pragma unroll
         for (int m = 0; m < MO; ++m)
@@ -165,6 +189,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) pay[q][j] = pa[q][j];
     }
+    if (pre && t + gridDim.x < A.ntiles) issue(t + gridDim.x);
     // ---- LDS atomic adds in FP64, in nonzero order.  Waves take turns; in
     // a wave, items in order, and the lanes of one ds_add_f64 that hit the
     // same entry are applied in ascending lane order (as for the integer
