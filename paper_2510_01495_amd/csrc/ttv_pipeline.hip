@@ -904,7 +904,10 @@ static_assert(4 * kSortedDig <= kNDig, "sorted rounds keep their counters in the
 // The first `gc` blocks classify this level's buckets (classify_item over
 // njobs*slices items); the others scatter its tiles.  Neither role reads what
 // the other writes in this launch.
-template <typename IdxT, int F, int PM, int MO>
+// REC: a deeper level's kernel, whose jobs all read the records of the level
+// before (loaded one round ahead); otherwise each job reads COO rows (the
+// first level) or records.
+template <typename IdxT, int F, int PM, int MO, bool REC>
 __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(WsView W, int level, int T, int Tnext, int maxlevel,
                                                              int slices, int gc, int smax) {
   constexpr int IPT = kScatterIPT;
@@ -945,6 +948,10 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
   for (int t = bid; t < ntiles; t += nsb) {
     const int jid = tj[t];
     const Job J = jobs[jid];
+    if (REC && J.src == kSrcRaw) {  // only first-level jobs read rows (uniform over the block)
+      if (threadIdx.x == 0) set_error(C, TTV_E_DEVICE);
+      continue;
+    }
     const int nd = 1 << J.r;
     const unsigned mask = (unsigned)nd - 1u;
     const unsigned* row = W.table() + (size_t)t * kNDig;
@@ -983,25 +990,38 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
         (PM == kPipeTTVSeg && srcR) ? to_global((const int32_t*)W.aux(J.src)) + J.start + b : (gptr<const int32_t>)nullptr;
     const gptr<int32_t> gaux =
         PM == kPipeTTVSeg ? to_global(W.aux(dst_of(level))) + J.start : (gptr<int32_t>)nullptr;
+    // Records of deeper levels: the next round's are loaded during this
+    // round's turns (issued after this round's loads; the turns' barriers
+    // wait only for LDS).  Segment-map-carrying records load as they come.
+    constexpr bool kPre = REC && PM != kPipeTTVSeg;
+    u64x2 nxr[IPT];
+    auto prefetch = [&](long long rb) {
+      const long long i0 = rb + (long long)w * RW + ln;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j)
+        if (i0 + j * 64 < n) nxr[j] = srcR[i0 + j * 64];
+    };
+    if (kPre) prefetch(0);
     for (long long rb = 0; rb < n; rb += RN) {
       uint64_t key[IPT], pay[IPT];
       unsigned dg[IPT];
       int32_t ax[IPT];
       {
         const long long i0 = rb + (long long)w * RW + ln;
-        if (srcR) {
+        if (REC || srcR) {
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
             key[j] = 0;
             pay[j] = 0;
             ax[j] = 0;
             if (i0 + j * 64 < n) {
-              const u64x2 r = srcR[i0 + j * 64];
+              const u64x2 r = kPre ? nxr[j] : srcR[i0 + j * 64];
               key[j] = r.x;
               pay[j] = r.y;
               if (PM == kPipeTTVSeg) ax[j] = srcX[i0 + j * 64];
             }
           }
+          if (kPre && rb + RN < n) prefetch(rb + RN);
         } else {
           const long long s0 = rb + (long long)w * RW;
           load_round<IdxT, F, PM, IPT, MO>(S, roff + s0, n - s0, stage[w], C, key, pay);
@@ -2062,8 +2082,12 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     const int slices = l == 1 ? kClassifySlices : 1;
     const int gc = std::min(gj * slices, 4 * cus);
     if (l == 1) prof_begin(TTV_PROF_SCATTER1, s);
-    hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO>), dim3(gc + gt), dim3(kScatterThreads), 0, s, W, l, T, Tn,
-                       P.levels, slices, gc, kSortedRounds);
+    if (l == 1)
+      hipLaunchKernelGGL((k_scatter<IdxT, F, PM, MO, false>), dim3(gc + gt), dim3(kScatterThreads), 0, s, W, l, T,
+                         Tn, P.levels, slices, gc, kSortedRounds);
+    else  // records only: the narrowest row class keeps the block's LDS small
+      hipLaunchKernelGGL((k_scatter<IdxT, F, PM, 3, true>), dim3(gc + gt), dim3(kScatterThreads), 0, s, W, l, T, Tn,
+                         P.levels, slices, gc, kSortedRounds);
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
