@@ -536,11 +536,11 @@ __device__ __forceinline__ void colscan_serial(WsView W, const Job& J, int j) {
   }
 }
 
-// Per-(tile, digit) bucket offsets and per-job digit totals.  Level 1 has a
-// few jobs of many tiles: items are (job, 64-digit chunk).  Deeper levels
-// have many jobs, mostly of few tiles: one block per such job; the jobs with
-// more tiles are listed per batch of 1024 jobs and their (job, chunk) items
-// spread over the blocks.
+// Per-(tile, digit) bucket offsets and per-job digit totals.  A single
+// tensor's first level is one job of many tiles: items are its 64-digit
+// chunks.  Otherwise (deeper levels, and the first level of a batch) jobs of
+// few tiles take one block each; the jobs with more tiles are listed per
+// batch of 1024 jobs and their (job, chunk) items spread over the blocks.
 __global__ __launch_bounds__(1024) void k_colscan(WsView W, int level) {
   __shared__ unsigned part[16][64];
   __shared__ int bigs[1024];
@@ -549,13 +549,10 @@ __global__ __launch_bounds__(1024) void k_colscan(WsView W, int level) {
   if (aborted(C)) return;
   const int njobs = clampi(C->njobs[level], W.L.jcap);
   const Job* jobs = W.jobs(level);
-  if (level == 1) {
-    for (long long it = blockIdx.x; it < (long long)njobs * 64; it += gridDim.x) {
-      const int j = (int)(it >> 6), ch = (int)(it & 63);
-      const Job J = jobs[j];
-      if (ch * 64 >= (1 << J.r)) continue;  // uniform over the block
-      colscan_chunk(W, J, j, ch, part);
-    }
+  if (level == 1 && njobs == 1) {  // one tensor: its many tiles in (64-digit chunk) items
+    const Job J = jobs[0];
+    for (int ch = blockIdx.x; ch < 64; ch += gridDim.x)
+      if (ch * 64 < (1 << J.r)) colscan_chunk(W, J, 0, ch, part);  // uniform over the block
     return;
   }
   for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
@@ -2076,8 +2073,7 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     if (l == 1) prof_begin(TTV_PROF_HIST1, s);
     hipLaunchKernelGGL((k_hist<IdxT, MO>), dim3(l == 1 ? gt : cus), dim3(kHistThreads), 0, s, W, l, T);
     if (l == 1) prof_end(TTV_PROF_HIST1, s);
-    hipLaunchKernelGGL(k_colscan, dim3(l == 1 ? std::min(std::max(1, P.count * 64), 4 * cus) : 2 * cus), dim3(1024),
-                       0, s, W, l);
+    hipLaunchKernelGGL(k_colscan, dim3(l == 1 && P.count == 1 ? 64 : 2 * cus), dim3(1024), 0, s, W, l);
     // classify blocks first (short), then the scatter's tiles
     const int slices = l == 1 ? kClassifySlices : 1;
     const int gc = std::min(gj * slices, 4 * cus);
