@@ -279,3 +279,58 @@ def test_fault_launch_returns_hip_error_before_the_device(monkeypatch):
     gv2 = (ctypes.c_void_p * 3)(None, None, 4096)
     assert lib.ttv_coo_backward_saved(ctypes.byref(d), 2, vecs, lens, dummy, dummy, gv2, dummy, dummy, big, 0,
                                       None) == -9
+
+
+def _bitlen(x):
+    return int(x).bit_length()
+
+
+def test_plan_properties_random_shapes():
+    """Host planner over random tensors (hypothesis): the remaining modes are
+    the complement of the contracted ones in ascending order; the key is the
+    dense mixed-radix number of their indices (first remaining mode most
+    significant: last stride 1, each stride the next one times the next
+    mode's length) spanning bitlen(range - 1) bits; the first digit is the
+    narrowest that brings the average occupied bucket under 0.6 x 2048
+    records (at most 12 bits and the key's width); after it, 12-bit levels
+    until at most 12 bits remain; the workspace holds one 16-byte record per
+    nonzero and grows with nnz."""
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=150, deadline=None, derandomize=True)
+    @hyp.given(st.lists(st.integers(1, 5000), min_size=2, max_size=6), st.integers(0, 3_000_000), st.data())
+    def check(dims, nnz, data):
+        d = len(dims)
+        ncon = data.draw(st.integers(1, d - 1))
+        con = sorted(data.draw(st.permutations(range(d)))[:ncon])
+        rc, info = _query(_desc(tuple(dims), nnz), con)
+        assert rc == 0
+        rem = [j for j in range(d) if j not in con]
+        assert info.nrem == len(rem) and list(info.rem_modes[:len(rem)]) == rem
+        assert [info.bits[i] for i in range(len(rem))] == [_bitlen(dims[j] - 1) for j in rem]
+        stride = 1
+        for i in range(len(rem) - 1, -1, -1):
+            assert info.stride[i] == stride
+            stride *= dims[rem[i]]
+        rng_ = stride
+        assert info.key_bits == _bitlen(rng_ - 1)
+        bits, r1 = info.key_bits, info.digit1_bits
+        cap = min(12, bits)
+        assert 0 <= r1 <= cap
+
+        def occupancy(r):
+            shift = bits - r
+            return nnz / -(-rng_ // (1 << shift))
+
+        if r1 < cap:
+            assert occupancy(r1) <= 0.6 * 2048
+        if r1 > 0:
+            assert occupancy(r1 - 1) > 0.6 * 2048
+        rest = max(0, bits - r1)
+        assert info.levels == min(8, 1 + -(-max(0, rest - 12) // 12))
+        assert info.workspace_bytes >= 16 * nnz
+        rc2, info2 = _query(_desc(tuple(dims), nnz + 100_000), con)
+        assert rc2 == 0 and info2.workspace_bytes >= info.workspace_bytes
+
+    check()
