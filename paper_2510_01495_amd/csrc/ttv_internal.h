@@ -152,7 +152,7 @@ struct Ctrl {
   int32_t ticket;
   int32_t error;          // first device-side error (TTV_E_* code), 0 if none
   long long total;        // records over all tensors
-  int32_t bm_done;        // bitmap blocks finished (the last one scans the block sums)
+  int32_t bm_done;        // reserved (zeroed by the init kernel)
   int32_t pad;
   unsigned long long dwords;  // words of the dense pool handed out
 };

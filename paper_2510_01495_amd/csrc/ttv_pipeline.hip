@@ -1130,13 +1130,13 @@ __global__ __launch_bounds__(kScatterThreads, MO <= 3 ? 3 : 2) void k_scatter(Ws
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // leaf numbering: popcount prefix of the leaf-start bitmap.  Every block
-// prefixes its words; the block that finishes last scans the block sums.
+// prefixes its words and stores its sum; a one-block kernel then scans the
+// block sums (the kernel boundary orders the two: no device-scope atomic per
+// block, whose release would write back the L2 on every block).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bitmap(WsView W) {
   constexpr int WPT = kBitmapWordsPerBlock / 256;
   __shared__ unsigned wsum[4];
-  __shared__ int s_last;
-  Ctrl* C = W.ctrl();
   const long long w0 = (long long)blockIdx.x * kBitmapWordsPerBlock + threadIdx.x * WPT;
   const gptr<const unsigned> bm = to_global((const unsigned*)W.bitmap());
   unsigned c[WPT];
@@ -1156,21 +1156,20 @@ __global__ __launch_bounds__(256) void k_bitmap(WsView W) {
     if (wi < W.L.words) wp[wi] = ex;
     ex += c[q];
   }
+  if (threadIdx.x == 0) W.blockpre()[blockIdx.x] = tot;
+}
+
+// Exclusive scan of k_bitmap's block sums, in place (one block).
+__global__ __launch_bounds__(1024) void k_bitmap_scan(WsView W) {
+  __shared__ unsigned wsum[1024 / 64];
   unsigned* bp = W.blockpre();
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&bp[blockIdx.x], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int done = __hip_atomic_fetch_add(&C->bm_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = done == (int)gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
   const long long n = W.L.wblocks;
   unsigned carry = 0;
-  for (long long b0 = 0; b0 < n; b0 += 256) {
+  for (long long b0 = 0; b0 < n; b0 += 1024) {
     const long long i = b0 + threadIdx.x;
-    const unsigned v = i < n ? __hip_atomic_load(&bp[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    const unsigned v = i < n ? bp[i] : 0u;
     unsigned t;
-    const unsigned e = block_excl_scan<256>(v, wsum, t);
+    const unsigned e = block_excl_scan<1024>(v, wsum, t);
     if (i < n) bp[i] = carry + e;
     carry += t;
   }
@@ -2087,6 +2086,7 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
     if (l == 1) prof_end(TTV_PROF_SCATTER1, s);
   }
   hipLaunchKernelGGL(k_bitmap, dim3((unsigned)std::max<long long>(1, P.L.wblocks)), dim3(256), 0, s, W);
+  hipLaunchKernelGGL(k_bitmap_scan, dim3(1), dim3(1024), 0, s, W);
   hipLaunchKernelGGL((k_leaves<F, PM>), dim3(4 * cus), dim3(kLeavesThreads), 0, s, W);
   prof_begin(TTV_PROF_FINISH, s);
   // three blocks per CU: the finish needs about 49 KB of LDS per block
