@@ -27,7 +27,10 @@ constexpr size_t kHdr = 256;                  // error word lives here (same off
 constexpr size_t kLdsBudget = 150 * 1024;     // dynamic LDS of one dense block
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr size_t kMaxWavesPerCU = 32;         // gfx950: 8 waves per SIMD, 4 SIMDs
-constexpr int kTile = kDenseThreads * kDenseIPT;
+// nonzeros per tile of the dense kernel for this tensor's value and index types
+int tile_of(const ttv_coo_desc* X) {
+  return kDenseThreads * dense_ipt(X->value_dtype == TTV_F64 ? kF64 : kC32, X->index_dtype == TTV_I64);
+}
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -52,7 +55,7 @@ size_t tile_lds_of(const ttv_coo_desc* X) {
                         row_width_class(X->order, X->stride_e, X->stride_j));
 }
 
-void finish_pass(Pass& p, long long nnz) {
+void finish_pass(Pass& p, long long nnz, int tile_nnz) {
   size_t acc = 0;
   p.acc_total = 0;
   for (int q = 0; q < p.nacc; ++q) {
@@ -63,7 +66,7 @@ void finish_pass(Pass& p, long long nnz) {
   // blocks per CU: LDS-limited, and at most kMaxWavesPerCU / 16 waves of a block
   const int bpc = (int)std::max<size_t>(
       1, std::min<size_t>(kMaxWavesPerCU / (kDenseThreads / 64), kLdsPerCU / std::max<size_t>(p.lds, 1)));
-  const long long ntiles = std::max<long long>(1, (nnz + kTile - 1) / kTile);
+  const long long ntiles = std::max<long long>(1, (nnz + tile_nnz - 1) / tile_nnz);
   p.grid = (int)std::max<long long>(1, std::min<long long>((long long)kAssumedCUs * bpc, ntiles));
 }
 
@@ -105,7 +108,7 @@ void plan_passes(const ttv_coo_desc* X, const int* modes, int nm, bool grad_vals
     }
     passes[0].grad_vals = true;
   }
-  for (int p = 0; p < npass; ++p) finish_pass(passes[p], X->nnz);
+  for (int p = 0; p < npass; ++p) finish_pass(passes[p], X->nnz, tile_of(X));
 }
 
 // Pipeline plan whose key is the single mode `m` (all other modes contracted).
@@ -135,7 +138,7 @@ void dense_base(const ttv_coo_desc* X, int flags, DenseArgs& A) {
     A.dims[j] = X->shape[j];
   }
   A.nnz = X->nnz;
-  A.ntiles = (X->nnz + kTile - 1) / kTile;
+  A.ntiles = (X->nnz + tile_of(X) - 1) / tile_of(X);
   A.order = X->order;
   A.validate = (flags & TTV_VALIDATE) ? 1 : 0;
 }

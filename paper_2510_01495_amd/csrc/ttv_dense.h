@@ -9,7 +9,10 @@
 namespace ttv {
 
 constexpr int kDenseThreads = 1024;
-constexpr int kDenseIPT = 2;
+// Nonzeros per lane and tile: 4 for FP32 values with 32-bit indices (fewer
+// ordered-add turns per nonzero; their registers allow it), 2 otherwise
+// (wider index rows and FP64 values would spill).
+__host__ __device__ constexpr int dense_ipt(int form, bool idx64) { return (form == kC32 && !idx64) ? 4 : 2; }
 constexpr int kDenseMaxAcc = 4;
 
 struct DenseArgs {

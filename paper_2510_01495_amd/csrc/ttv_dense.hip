@@ -30,13 +30,13 @@ namespace {
 
 constexpr int NT = kDenseThreads;
 constexpr int NW = NT / 64;
-constexpr int IPT = kDenseIPT;
-constexpr int TA = NT * IPT;  // nonzeros per tile
 
 template <typename IdxT, int F, int MO, int NACC>
 __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs A) {
   using FO = FormOps<F>;
   using In = typename FO::In;
+  constexpr int IPT = dense_ipt(F, sizeof(IdxT) == 8);
+  constexpr int TA = NT * IPT;  // nonzeros per tile
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // layout: FP64 accumulators | row stage IdxT[NW][64*MO] | staged factor vectors
   double* accs = reinterpret_cast<double*>(smem);
