@@ -1445,7 +1445,9 @@ __global__ __launch_bounds__(kFinishThreads, 4) void k_finish(WsView W, int spin
   // Region A holds, by leaf kind: the sort's relative keys and positions
   // (sk, si); a sort-free leaf's row sums and row keys (acc, rkey); a dense
   // leaf's sums by key (acc).  With the digit counters (cnt) the block
-  // needs about 49 KB of LDS, so three blocks share a CU.
+  // needs about 49 KB of LDS, room for three blocks per CU; at 128 VGPRs per
+  // lane (four waves per SIMD) two of them run per CU.  Bounds that force six
+  // waves per SIMD spill about 160 bytes per lane and measured slower.
   __shared__ __attribute__((aligned(16))) unsigned char smA[kCap * 8 + kCap * 2];
   unsigned* const sk = reinterpret_cast<unsigned*>(smA);
   unsigned short* const si = reinterpret_cast<unsigned short*>(smA + kCap * 4);
@@ -2089,7 +2091,8 @@ static int launch_impl(const PipePlan& P, void* ws, hipStream_t s) {
   hipLaunchKernelGGL(k_bitmap_scan, dim3(1), dim3(1024), 0, s, W);
   hipLaunchKernelGGL((k_leaves<F, PM>), dim3(4 * cus), dim3(kLeavesThreads), 0, s, W);
   prof_begin(TTV_PROF_FINISH, s);
-  // three blocks per CU: the finish needs about 49 KB of LDS per block
+  // three blocks per CU, as the LDS would allow; registers keep two resident
+  // per CU, and a block that starts once one ends finds the tickets gone
   hipLaunchKernelGGL((k_finish<IdxT, F, PM>), dim3(3 * cus), dim3(kFinishThreads), 0, s, W,
                      fault_on("spin") ? 0 : P.spin_limit);
   prof_end(TTV_PROF_FINISH, s);
